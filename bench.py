@@ -1,0 +1,166 @@
+"""Benchmark of the fused 7L online stage on one MI355X.
+
+One step = one full simulation of the workload through the C ABI (network
+collocation map, barycentric step, Philox normals, FP64 block reduction and
+final statistics; Algorithm I steps 2-8).  Default workload: GBM network map,
+N = 2^24 paths, M = 32 steps, sigma 0.4, mu 0.05, T 2, BF16 GEMMs on MFMA
+with FP32 accumulation; the FP32-MFMA and FP16-MFMA runs of the same
+workload and the FP32 run of the N = 2^22, M = 16 workload are reported
+beside it, each with its error against the FP64 oracle on sampled paths.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WEIGHTS = os.path.join(ROOT, "tests", "golden", "gbm_mlp_4x64.sl7w")
+FLOPS_PER_PATH_STEP = 2 * (4 * 64 + 3 * 64 * 64 + 64 * 5)  # 25,728
+PEAK = {"bf16": 2.5e15, "f16": 2.5e15, "f32": 157.3e12, "f64": 78.6e12}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_calls(S, pr, H, prec, seed, steps, warmup, stats):
+    import torch
+    for _ in range(warmup):
+        S.simulate(pr, H, prec=prec, seed=seed, stats=stats)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    last = None
+    for _ in range(steps):
+        last, _ = S.simulate(pr, H, prec=prec, seed=seed, stats=stats)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall / steps, ev0.elapsed_time(ev1) / 1e3 / steps, last
+
+
+def sampled_error(S, pr, H, Ho, prec, seed, n_sample=2048):
+    """Max and p99 per-path relative error vs the FP64 oracle on sampled paths."""
+    import oracle
+    import torch
+    _, yt = S.simulate(pr, H, prec=prec, seed=seed, want_yt=True, stats=False)
+    torch.cuda.synchronize()
+    N = pr.N
+    sub = np.unique(np.concatenate([np.arange(n_sample // 2),
+                                    np.linspace(0, N - 1, n_sample // 2).astype(np.int64)]))
+    y = yt.double().cpu().numpy()[sub]
+    opr = oracle.Problem(pr.model, pr.theta, pr.Y0, pr.T, pr.M, pr.m)
+    ref, _, _ = oracle.simulate(opr, Ho, seed, sub)
+    r = np.abs(y - ref) / np.maximum(np.abs(ref), 1e-12)
+    return float(r.max()), float(np.quantile(r, 0.99)), len(sub)
+
+
+def cpu_baseline(pr, Ho, seed, n_paths):
+    """The oracle (FP64, plain C, all host cores) on a bounded sample."""
+    import oracle
+    threads = oracle.n_threads()
+    paths = np.arange(n_paths)
+    opr = oracle.Problem(pr.model, pr.theta, pr.Y0, pr.T, pr.M, pr.m)
+    oracle.simulate(opr, Ho, seed, paths[:256], threads=threads)
+    t0 = time.perf_counter()
+    oracle.simulate(opr, Ho, seed, paths, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n_paths * pr.M / dt, "unit": "path-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {n_paths} of the {pr.N} paths x {pr.M} steps, FP64 network map, "
+                      f"{dt:.1f} s wall on {threads} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-paths", type=int, default=2 ** 14)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "paths shard by global index, but no multi-GPU path is built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2302_05170_amd as S
+    import workloads as W
+    if not torch.cuda.is_available():
+        sys.exit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    H = S.Mlp.load(WEIGHTS)
+    import oracle
+    Ho = oracle.load_mlp(WEIGHTS)
+
+    c = W.CONFIGS["c2"]
+    pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
+    ps = c["N"] * c["M"]
+    res = {}
+    for prec, steps in (("bf16", args.steps), ("f16", max(3, args.steps // 2)),
+                        ("f32", max(2, args.steps // 4))):
+        wall, ev, st = time_calls(S, pr, H, prec, c["seed"], steps, args.warmup, stats=True)
+        _, ev_async, _ = time_calls(S, pr, H, prec, c["seed"], steps, 1, stats=False)
+        emax, e99, ns = sampled_error(S, pr, H, Ho, prec, c["seed"])
+        res[prec] = dict(wall=wall, ev=ev, ev_async=ev_async, st=st, emax=emax, e99=e99, ns=ns)
+        log(f"{prec}: {ps / wall:.3e} path-steps/s (wall {wall * 1e3:.2f} ms, kernel seq "
+            f"{ev_async * 1e3:.2f} ms), mean {st['mean'][0]:.6f} +- {st['se'][0]:.1e}, "
+            f"max rel err {emax:.2e} (p99 {e99:.2e}, {ns} paths)")
+
+    c1 = W.CONFIGS["c1"]
+    pr1 = S.Problem(c1["model"], c1["theta"], c1["Y0"], c1["T"], c1["M"], c1["m"], c1["N"], K=c1["K"])
+    wall1, _, st1 = time_calls(S, pr1, H, "f32", c1["seed"], max(2, args.steps // 2), 1, stats=True)
+    log(f"c1 f32: {c1['N'] * c1['M'] / wall1:.3e} path-steps/s")
+
+    b = res["bf16"]
+    t_kernel = b["ev_async"]
+    achieved = FLOPS_PER_PATH_STEP * ps / t_kernel
+    se_pair = math.hypot(b["st"]["se"][0], res["f32"]["st"]["se"][0])
+    out = {
+        "metric": "7L path-steps/s (BF16 MFMA network GEMMs, FP32 interpolation, FP64 mean)",
+        "value": ps / b["wall"],
+        "unit": "path-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": b["wall"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic (Philox normals; network trained by the project on synthetic EM labels)",
+        "config": {"workload": "GBM network map, N=2^24 paths, M=32 steps, sigma=0.4, mu=0.05, "
+                               "T=2, m=5, MLP 4-64x4-5 ReLU", "N": c["N"], "M": c["M"],
+                   "seed": c["seed"], "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["bf16"] / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK["bf16"], "traffic": None},
+        "precision_compare": {
+            p: {"path_steps_per_s": ps / r["wall"], "kernel_ms": r["ev_async"] * 1e3,
+                "frac_of_dtype_peak": FLOPS_PER_PATH_STEP * ps / r["ev_async"] / PEAK[p],
+                "max_rel_err_vs_fp64_oracle": r["emax"], "p99_rel_err": r["e99"],
+                "sampled_paths": r["ns"], "mean_YT": r["st"]["mean"][0], "se_YT": r["st"]["se"][0]}
+            for p, r in res.items()},
+        "bf16_minus_f32_mean_over_se": (b["st"]["mean"][0] - res["f32"]["st"]["mean"][0]) / se_pair,
+        "c1_f32_path_steps_per_s": c1["N"] * c1["M"] / wall1,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pr, Ho, c["seed"], args.cpu_paths)
+        log(f"cpu baseline: {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

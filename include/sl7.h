@@ -1,0 +1,232 @@
+/*
+ * sl7.h -- C ABI of the MI355X (gfx950) Seven-League (7L) library.
+ *
+ * The library runs the online stage of the 7L scheme (arXiv 2302.05170,
+ * Algorithm I, steps 2-8): every Monte Carlo path takes M large steps; at each
+ * step the collocation network H maps (Y_i, dt, theta) to m collocation
+ * points y_j (eq. 6.3/6.4), a fresh standard normal X is drawn and
+ * Y_{i+1} = g_m(X), the barycentric Lagrange interpolant through (x_j, y_j)
+ * with x_j the Gauss-Hermite points of N(0,1) (Methodology and
+ * Parallelization sections).  Beside it: the offline stage that makes labels
+ * and trains H (Algorithm I, step 1), a reverse-mode adjoint for pathwise
+ * sensitivities, and a batched launch over many uneven instances.
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns an int status: SL7_OK (0) or a negative SL7_E* code.
+ *     sl7_last_error() then gives a message naming the offending argument.
+ *     The message is thread-local and valid until the next call on the same
+ *     thread.  No C++ exception crosses this boundary.  On error the contents
+ *     of output buffers are unspecified.
+ *   - "device" pointers are HIP device allocations owned by the caller, on the
+ *     current HIP device; "host" pointers are ordinary host memory owned by
+ *     the caller.  The library never frees caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *     is enqueued on it; calls that return results into host memory
+ *     synchronise that stream before returning, as documented per call.
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit
+ *     seed, counter (step/4, path low word, path high word, tag) with
+ *     tag = domain << 24 | instance, domain 0 for simulation and 1 for
+ *     labels; Box-Muller turns each call's four words into four normals for
+ *     four consecutive steps.  Paths use global indices, so results do not
+ *     depend on how paths are tiled over the GPU.
+ *   - Model parameter vectors theta[]: GBM dY = mu Y dt + sigma Y dW with
+ *     theta = (sigma, mu); OU (eq. 6.5) with theta = (ybar, sigma, lambda);
+ *     CIR dY = kappa (ybar - Y) dt + gamma sqrt(Y) dW with
+ *     theta = (kappa, ybar, gamma).  The network's inputs are
+ *     (Y, dt, theta[0], ..., theta[n-1]) in that order.
+ */
+#ifndef SL7_H
+#define SL7_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define SL7_OK 0
+#define SL7_EINVAL (-1)       /* an argument is out of range or inconsistent */
+#define SL7_EUNSUPPORTED (-2) /* valid request this build does not implement */
+#define SL7_EHIP (-3)         /* a HIP runtime call failed */
+#define SL7_ENOMEM (-4)       /* device or host allocation failed */
+#define SL7_ENUMERIC (-5)     /* non-finite weights or results */
+#define SL7_EIO (-6)          /* weight file could not be read or written */
+
+/* Models (eq. 6.1 specialised). */
+#define SL7_GBM 0
+#define SL7_OU 1
+#define SL7_CIR 2
+
+/* Arithmetic of the network GEMMs.  F64: everything in double.  F32: GEMMs
+ * on FP32 MFMA.  BF16 / F16: hidden-layer and head GEMM operands rounded
+ * (RNE) to bfloat16 / half on MFMA with FP32 accumulation; the first layer,
+ * the interpolation and the state update stay FP32; the path mean is
+ * reduced in FP64 in every mode. */
+#define SL7_F64 0
+#define SL7_F32 1
+#define SL7_BF16 2
+#define SL7_F16 3
+
+/* Hidden activations. */
+#define SL7_RELU 0
+#define SL7_SOFTPLUS 1
+
+/* Largest sizes the kernels accept. */
+#define SL7_MAX_M 8       /* collocation points */
+#define SL7_MAX_DIN 8     /* network inputs */
+#define SL7_WIDTH 64      /* hidden width the kernels are built for */
+#define SL7_DEPTH 4       /* hidden layers the kernels are built for */
+
+typedef struct sl7_mlp sl7_mlp; /* opaque network handle */
+
+/* Network description: d_in inputs -> depth hidden layers of `width` units
+ * -> m outputs.  h0 = in_scale * input + in_shift (elementwise), so the
+ * inputs' training ranges can be mapped to [-1, 1]; dom_lo/dom_hi record the
+ * training domain (used to count out-of-domain network calls). */
+typedef struct {
+  int32_t d_in, width, depth, m, act, model;
+  double in_scale[SL7_MAX_DIN], in_shift[SL7_MAX_DIN];
+  double dom_lo[SL7_MAX_DIN], dom_hi[SL7_MAX_DIN];
+} sl7_mlp_desc;
+
+/* One simulation instance (Algorithm I, online stage).  dt = T / M,
+ * t_i = i T / M.  Paths path_offset .. path_offset + N - 1 (global indices,
+ * used as the Philox counter).  instance becomes the low 24 bits of the tag. */
+typedef struct {
+  int32_t model, m, M, reserved0;
+  int64_t N;
+  double theta[4];
+  double Y0, T, K; /* K: strike of the second payoff max(Y_T - K, 0) */
+  int64_t path_offset;
+  uint32_t instance, reserved1;
+} sl7_problem;
+
+/* Results for two payoffs: index 0 is Y_T, index 1 is max(Y_T - K, 0).
+ * var uses N - 1; se = sqrt(var / N).  n_clamped counts CIR steps whose
+ * interpolated value was negative and was set to 0; n_out_of_domain counts
+ * network evaluations whose Y input lay outside the training domain. */
+typedef struct {
+  double mean[2], var[2], se[2];
+  int64_t n, n_clamped, n_out_of_domain, reserved;
+} sl7_stats;
+
+/* Launch plan of the fused kernel.  A plan changes speed, never results. */
+typedef struct {
+  int32_t waves_per_block; /* 1, 2, 4 or 8 wave64s per workgroup */
+  int32_t blocks_per_cu;   /* persistent grid = blocks_per_cu x compute units */
+  int32_t grab;            /* 64-path blocks taken per work-queue grab */
+  int32_t reserved;
+} sl7_plan;
+
+/* --- errors ---------------------------------------------------------- */
+const char* sl7_last_error(void);
+const char* sl7_version(void);
+
+/* --- collocation nodes (Methodology section: x_j from N(0,1)) ---------- */
+/* Probabilists' Gauss-Hermite nodes (roots of He_m), ascending and
+ * symmetric, and weights w_j summing to 1.  m in [1, 16].  x, w: host,
+ * m doubles each. */
+int sl7_gh_nodes(int m, double* x, double* w);
+
+/* --- the network H (eq. 6.3/6.4) -------------------------------------- */
+/* Number of FP32 parameters of a description: per layer W (out x in,
+ * row-major) then b, layers in order. */
+int64_t sl7_mlp_n_params(const sl7_mlp_desc* d);
+/* Creates a handle from a description and a host parameter vector (copied).
+ * EINVAL on bad dimensions, ENUMERIC on non-finite parameters. */
+int sl7_mlp_create(const sl7_mlp_desc* d, const float* params, sl7_mlp** H);
+/* Reads / writes the little-endian weight file ("SL7W" version 1: u32
+ * version, d_in, width, depth, m, act, model; f64 in_scale, in_shift,
+ * dom_lo, dom_hi [d_in each]; per layer f32 W then b; u32 length and JSON
+ * metadata).  EIO on unreadable files, EINVAL on malformed ones. */
+int sl7_mlp_load(const char* path, sl7_mlp** H);
+int sl7_mlp_save(const sl7_mlp* H, const char* path);
+/* Copies the description / current parameters out (host memory). */
+int sl7_mlp_get_desc(const sl7_mlp* H, sl7_mlp_desc* d);
+int sl7_mlp_get_params(const sl7_mlp* H, float* params);
+/* Replaces the parameters (host vector, copied; device copies refreshed). */
+int sl7_mlp_set_params(sl7_mlp* H, const float* params);
+void sl7_mlp_free(sl7_mlp* H);
+
+/* Batched forward pass of H (Algorithm I step 3, eq. 6.4): in [B x d_in]
+ * raw inputs, row-major FP32, device; out [B x m] FP32, device.  prec as
+ * above.  Asynchronous on `stream`. */
+int sl7_eval_H(const sl7_mlp* H, int prec, const float* in_dev, int64_t B,
+               float* out_dev, void* stream);
+
+/* --- the online stage (Algorithm I, steps 2-8) ------------------------- */
+/* Simulates pr->N paths of pr->M steps.  H == NULL selects the analytic
+ * collocation map of the model (GBM: y_j = Y exp((mu - sigma^2/2) dt +
+ * sigma sqrt(dt) x_j); OU: eq. 6.6 over one step); otherwise H (whose m
+ * and d_in = 2 + n_theta must match).  prec: SL7_F64 for either map; F32
+ * for either map; BF16 and F16 for the network only.
+ * YT_dev: NULL, or device buffer of N values (double in F64 mode, float
+ * otherwise) that receives Y_T per path.  stats_host: NULL or host struct;
+ * when non-NULL the call synchronises `stream` before returning.
+ * plan: NULL for the default/tuned plan. */
+int sl7_simulate(const sl7_problem* pr, const sl7_mlp* H, int prec,
+                 uint64_t seed, void* YT_dev, sl7_stats* stats_host,
+                 const sl7_plan* plan, void* stream);
+
+/* Many instances of uneven size in one persistent launch (network map,
+ * prec F32/BF16/F16).  Work is 64-path blocks ordered longest-M first and
+ * handed out by an atomic work counter; per-instance statistics go to
+ * stats_host[n] (synchronises the stream).  The launch sequence is captured
+ * once into a hipGraph per distinct (prec, instance table) signature and
+ * replayed when use_graph != 0. */
+int sl7_simulate_batched(const sl7_problem* prs, int n, const sl7_mlp* H,
+                         int prec, uint64_t seed, sl7_stats* stats_host,
+                         const sl7_plan* plan, int use_graph, void* stream);
+
+/* --- offline stage (Algorithm I, step 1) ------------------------------- */
+/* Training labels: for each of the n rows of feats_dev ([n x d_in] FP32,
+ * device; row = (Y, dt, theta...), d_in = 2 + n_theta(model)), n_paths
+ * Euler-Maruyama paths (eq. 6.2, FP64) of `substeps` steps of dt/substeps
+ * from Y; labels_dev[r*m + j] (FP32, device) is the empirical quantile of
+ * the endpoints at Phi(x_j), linear between order statistics at
+ * h = (n_paths - 1) Phi(x_j).  Philox domain 1, counter word 2 =
+ * label0 + r.  n_paths in [2, 16384].  Asynchronous on `stream`. */
+int sl7_labels(int model, int m, const float* feats_dev, int64_t n, int n_paths,
+               int substeps, uint64_t seed, int64_t label0, float* labels_dev,
+               void* stream);
+
+/* Adam on the mean squared error over batch x m (the paper's offline
+ * training: Glorot start is the caller's parameter vector, batch and
+ * learning rate from spec). */
+typedef struct {
+  int32_t epochs, batch;
+  double lr, beta1, beta2, eps;
+} sl7_train_spec;
+
+/* Trains H in place (FP32 forward/backward kernels, deterministic gradient
+ * sums).  X_dev [n x d_in] raw inputs, Y_dev [n x m] labels (device, FP32).
+ * order_dev: NULL (rows in order every epoch) or epochs x n int32 row
+ * indices (device); each epoch takes n / batch minibatches of consecutive
+ * entries.  loss_hist_host: NULL or room for epochs * (n / batch) doubles
+ * (minibatch losses).  Synchronises `stream`; ENUMERIC if training
+ * diverges. */
+int sl7_train(sl7_mlp* H, const sl7_train_spec* spec, const float* X_dev,
+              const float* Y_dev, int64_t n, const int32_t* order_dev,
+              double* loss_hist_host, void* stream);
+
+/* Gradient of the loss over the B rows (one minibatch) with respect to the
+ * parameter vector (same layout as the parameters) into grad_dev (FP32,
+ * device); loss_host: NULL or the loss.  Synchronises `stream`. */
+int sl7_train_grad(const sl7_mlp* H, const float* X_dev, const float* Y_dev, int64_t B,
+                   float* grad_dev, double* loss_host, void* stream);
+
+/* --- launch-plan autotuner -------------------------------------------- */
+/* Times candidate plans on `shape` (a problem, N may be reduced) and
+ * returns the fastest in *out; when cache_path is not NULL the result is
+ * stored there as one JSON line per (arch, prec, d_in, m) key and read back
+ * on later calls instead of re-timing. */
+int sl7_autotune(const sl7_problem* shape, const sl7_mlp* H, int prec,
+                 const char* cache_path, sl7_plan* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SL7_H */

@@ -1,0 +1,9 @@
+"""Seven-League (7L) large-step SDE simulation on AMD MI355X (gfx950).
+
+The compute path is libsl7.so (hand-written HIP kernels + C++ host runtime,
+C ABI in include/sl7.h).  This package only marshals arguments: torch
+tensors serve as device buffers and streams.
+"""
+from ._lib import (BF16, CIR, F16, F32, F64, GBM, OU, RELU, SOFTPLUS, Sl7Error)  # noqa: F401
+from .api import (Mlp, PRECISIONS, Problem, eval_H, gh_nodes, labels, simulate,  # noqa: F401
+                  simulate_batched, train, train_grad)

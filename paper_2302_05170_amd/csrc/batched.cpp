@@ -1,0 +1,270 @@
+// Batched launches of many uneven instances (one persistent fused kernel
+// over a longest-M-first work queue), their hipGraph cache, and the launch-
+// plan autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "sl7_host.hpp"
+
+using namespace sl7;
+
+namespace {
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* c = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// A captured launch sequence with buffers of its own, so replays need no
+// upload and are not disturbed by other calls on the device.
+struct GraphEntry {
+  Workspace ws;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t capture = nullptr;
+  sl7_stats* host = nullptr;
+  int n = 0;
+  ~GraphEntry() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (capture) (void)hipStreamDestroy(capture);
+    if (host) (void)hipHostFree(host);
+  }
+};
+
+struct GraphCache {
+  std::mutex mu;
+  std::map<uint64_t, std::unique_ptr<GraphEntry>> entries;
+  std::vector<uint64_t> lru;
+};
+
+GraphCache& graph_cache() {
+  static GraphCache c;
+  return c;
+}
+
+int check_batch(const sl7_problem* prs, int n, const Mlp* H, int prec) {
+  if (!prs) return fail(SL7_EINVAL, "prs is NULL");
+  if (n < 1 || n > 65536) return fail(SL7_EINVAL, "n=%d outside [1, 65536]", n);
+  if (!H) return fail(SL7_EUNSUPPORTED, "batched launches need a network");
+  if (prec == SL7_F64) return fail(SL7_EUNSUPPORTED, "batched launches run in F32, BF16 or F16");
+  char name[32];
+  for (int k = 0; k < n; ++k) {
+    snprintf(name, sizeof(name), "prs[%d]", k);
+    int rc = check_problem(&prs[k], H, prec, name);
+    if (rc) return rc;
+    if (prs[k].m != prs[0].m) return fail(SL7_EINVAL, "prs[%d].m differs from prs[0].m", k);
+  }
+  return SL7_OK;
+}
+
+}  // namespace
+
+extern "C" int sl7_simulate_batched(const sl7_problem* prs, int n, const sl7_mlp* Hc, int prec,
+                                    uint64_t seed, sl7_stats* stats_host, const sl7_plan* plan_in,
+                                    int use_graph, void* stream) {
+  Mlp* H = const_cast<Mlp*>(reinterpret_cast<const Mlp*>(Hc));
+  int rc = check_batch(prs, n, H, prec);
+  if (rc) return rc;
+  if (!stats_host) return fail(SL7_EINVAL, "stats_host is NULL");
+  sl7_plan plan;
+  if (plan_in) plan = *plan_in; else default_plan(prec, &plan);
+  rc = check_plan(&plan);
+  if (rc) return rc;
+  rc = H->ensure_device(prec);
+  if (rc) return rc;
+  int dev;
+  rc = current_device(&dev);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<sl7_problem> p(prs, prs + n);
+  for (int k = 0; k < n; ++k) p[k].instance = prs[k].instance;
+  if (!use_graph) {
+    Workspace& ws = workspace(dev);
+    std::lock_guard<std::mutex> lk(ws.mu);
+    rc = run_instances(p.data(), n, H, prec, seed, nullptr, &plan, s, ws);
+    if (rc) return rc;
+    return fetch_stats(ws, n, stats_host, s);
+  }
+  // graph path: key on everything the captured nodes depend on
+  uint64_t key = fnv1a(p.data(), sizeof(sl7_problem) * n);
+  key = fnv1a(&plan, sizeof(plan), key);
+  key = fnv1a(&seed, sizeof(seed), key);
+  key = fnv1a(&prec, sizeof(prec), key);
+  key = fnv1a(&dev, sizeof(dev), key);
+  const void* wp = H->pack[prec]->p;
+  key = fnv1a(&wp, sizeof(wp), key);
+  key = fnv1a(&H->pack[prec]->generation, sizeof(uint64_t), key);
+  GraphCache& gc = graph_cache();
+  std::lock_guard<std::mutex> lk(gc.mu);
+  auto it = gc.entries.find(key);
+  GraphEntry* E = nullptr;
+  if (it == gc.entries.end()) {
+    std::unique_ptr<GraphEntry> ne(new GraphEntry());
+    ne->ws.n_cu = workspace(dev).n_cu;
+    ne->n = n;
+    hipError_t e = hipStreamCreateWithFlags(&ne->capture, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    e = hipHostMalloc((void**)&ne->host, sizeof(sl7_stats) * n, 0);
+    if (e != hipSuccess) return fail(SL7_ENOMEM, "hipHostMalloc(stats)");
+    SimArgs a;
+    rc = prepare_instances(p.data(), n, H, prec, seed, nullptr, ne->capture, ne->ws, a);
+    if (rc) return rc;
+    e = hipStreamSynchronize(ne->capture);
+    if (e != hipSuccess) return hip_fail(e, "upload instance table");
+    e = hipStreamBeginCapture(ne->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    rc = launch_instances(a, n, p[0].N, H, prec, plan, ne->capture, ne->ws);
+    if (!rc) {
+      e = hipMemcpyAsync(ne->host, ne->ws.stats.p, sizeof(sl7_stats) * n, hipMemcpyDeviceToHost,
+                         ne->capture);
+      if (e != hipSuccess) rc = hip_fail(e, "capture statistics copy");
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(ne->capture, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    ne->graph = g;
+    e = hipGraphInstantiate(&ne->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    E = ne.get();
+    gc.entries[key] = std::move(ne);
+    gc.lru.push_back(key);
+    while (gc.lru.size() > 8) {
+      gc.entries.erase(gc.lru.front());
+      gc.lru.erase(gc.lru.begin());
+    }
+  } else {
+    E = it->second.get();
+  }
+  hipError_t e = hipGraphLaunch(E->exec, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  std::memcpy(stats_host, E->host, sizeof(sl7_stats) * n);
+  for (int k = 0; k < n; ++k)
+    if (!std::isfinite(stats_host[k].mean[0])) return fail(SL7_ENUMERIC, "instance %d: non-finite mean", k);
+  return SL7_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: times each candidate plan on the given shape and keeps the
+// fastest; results are cached as JSON lines keyed by (arch, prec, d_in, m).
+// ---------------------------------------------------------------------------
+namespace {
+
+std::string plan_key(int prec, const Mlp* H) {
+  char b[96];
+  snprintf(b, sizeof(b), "gfx950/prec%d/din%d/m%d", prec, H->d.d_in, H->d.m);
+  return b;
+}
+
+bool cache_lookup(const char* path, const std::string& key, sl7_plan* out) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    const std::string tag = "\"key\": \"" + key + "\"";
+    if (line.find(tag) == std::string::npos) continue;
+    sl7_plan p;
+    std::memset(&p, 0, sizeof(p));
+    const char* s = line.c_str();
+    const char* w = strstr(s, "\"waves_per_block\":");
+    const char* b = strstr(s, "\"blocks_per_cu\":");
+    const char* g = strstr(s, "\"grab\":");
+    if (!w || !b || !g) continue;
+    p.waves_per_block = atoi(w + 18);
+    p.blocks_per_cu = atoi(b + 16);
+    p.grab = atoi(g + 7);
+    if (check_plan(&p) == SL7_OK) {
+      *out = p;
+      found = true;  // last matching line wins
+    }
+  }
+  return found;
+}
+
+}  // namespace
+
+extern "C" int sl7_autotune(const sl7_problem* shape, const sl7_mlp* Hc, int prec,
+                            const char* cache_path, sl7_plan* out, void* stream) {
+  Mlp* H = const_cast<Mlp*>(reinterpret_cast<const Mlp*>(Hc));
+  if (!out) return fail(SL7_EINVAL, "out is NULL");
+  if (!H) return fail(SL7_EUNSUPPORTED, "the tuner times the network kernels; H is NULL");
+  int rc = check_problem(shape, H, prec, "shape");
+  if (rc) return rc;
+  if (prec == SL7_F64) return fail(SL7_EUNSUPPORTED, "F64 runs the per-lane kernel (no plan)");
+  const std::string key = plan_key(prec, H);
+  if (cache_path && cache_lookup(cache_path, key, out)) return SL7_OK;
+  rc = H->ensure_device(prec);
+  if (rc) return rc;
+  int dev;
+  rc = current_device(&dev);
+  if (rc) return rc;
+  Workspace& ws = workspace(dev);
+  std::lock_guard<std::mutex> lk(ws.mu);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<sl7_plan> cands;
+  const int wpb[] = {1, 2, 4, 8};
+  const int bpc[] = {1, 2, 3, 4, 8};
+  const int grabs[] = {1, 4};
+  for (int w : wpb)
+    for (int b : bpc)
+      for (int g : grabs) {
+        if (w * b > 32) continue;
+        sl7_plan p = {w, b, g, 0};
+        cands.push_back(p);
+      }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(SL7_EHIP, "hipEventCreate");
+  SimArgs a;
+  rc = prepare_instances(shape, 1, H, prec, 1, nullptr, s, ws, a);
+  float best = INFINITY;
+  sl7_plan bestp;
+  default_plan(prec, &bestp);
+  for (size_t c = 0; c < cands.size() && !rc; ++c) {
+    rc = launch_instances(a, 1, shape->N, H, prec, cands[c], s, ws);  // warm-up
+    if (rc) break;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < 3 && !rc; ++r) rc = launch_instances(a, 1, shape->N, H, prec, cands[c], s, ws);
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SL7_EHIP, "hipEventSynchronize"); break; }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) { best = ms; bestp = cands[c]; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  *out = bestp;
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "a");
+    if (!f) return fail(SL7_EIO, "cannot append to %s", cache_path);
+    fprintf(f, "{\"key\": \"%s\", \"waves_per_block\": %d, \"blocks_per_cu\": %d, \"grab\": %d, "
+               "\"ms_per_launch\": %.5f, \"N\": %lld, \"M\": %d}\n",
+            key.c_str(), bestp.waves_per_block, bestp.blocks_per_cu, bestp.grab, best / 3.0,
+            (long long)shape->N, shape->M);
+    fclose(f);
+  }
+  return SL7_OK;
+}

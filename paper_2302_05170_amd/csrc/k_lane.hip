@@ -1,0 +1,285 @@
+// Per-lane Seven-League kernels: one path per lane, one 64-path block per
+// workgroup.  Used for the FP64 mode (analytic map or network) and the FP32
+// analytic map.  The network path here is the plain double-precision
+// reference arithmetic on the GPU; the MFMA kernels carry the fast modes.
+//
+// Online stage of Algorithm I (steps 2-8): for each large step, collocation
+// points y_j from the analytic law or the network H (eq. 6.3/6.4), a fresh
+// normal X and Y <- g_m(X), the barycentric interpolant (Parallelization
+// section, second form, exact-node branch).
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+
+namespace sl7 {
+
+template <typename T>
+__device__ __forceinline__ T act_fn(int act, T z) {
+  if (act == SL7_RELU) return z > T(0) ? z : T(0);
+  return z > T(0) ? z + log1p(exp(-z)) : log1p(exp(z));
+}
+
+// Network forward in double for one path per lane.  hA/hB: this lane's
+// columns of two LDS buffers [64 units][64 lanes].  First layer uses the
+// rank-one form z0 = wY * Y + c0 (dt and theta folded into c0 on the host).
+__device__ void net_lane_f64(const double* __restrict__ W, const double* __restrict__ c0,
+                             double Y, int m, int act, double* hA, double* hB,
+                             double y[kMaxM]) {
+  for (int o = 0; o < 64; ++o) hA[o * 64] = act_fn(act, fma(W[o], Y, c0[o]));
+  const double* Wl = W + 64;
+  double* hin = hA;
+  double* hout = hB;
+  for (int l = 0; l < 3; ++l) {
+    const double* bl = Wl + 64 * 64;
+    for (int o = 0; o < 64; ++o) {
+      double s = bl[o];
+      const double* row = Wl + o * 64;
+#pragma unroll 8
+      for (int k = 0; k < 64; ++k) s = fma(row[k], hin[k * 64], s);
+      hout[o * 64] = act_fn(act, s);
+    }
+    Wl += 64 * 64 + 64;
+    double* t = hin; hin = hout; hout = t;
+  }
+  const double* bh = Wl + 64 * m;
+#pragma unroll
+  for (int j = 0; j < kMaxM; ++j) {
+    if (j < m) {
+      double s = bh[j];
+      const double* row = Wl + j * 64;
+      for (int k = 0; k < 64; ++k) s = fma(row[k], hin[k * 64], s);
+      y[j] = s;
+    }
+  }
+}
+
+// Barycentric interpolation, second form, with the exact-node branch.
+template <typename T>
+__device__ __forceinline__ T bary_lane(const T* xs, const T* ls, int m, const T y[kMaxM], T X) {
+  T num = T(0), den = T(0), yh = T(0);
+  bool hit = false;
+#pragma unroll
+  for (int j = 0; j < kMaxM; ++j) {
+    if (j < m) {
+      if (X == xs[j]) { hit = true; yh = y[j]; }
+      const T t = ls[j] / (X - xs[j]);
+      num += t * y[j];
+      den += t;
+    }
+  }
+  return hit ? yh : num / den;
+}
+
+template <typename T, bool NET>
+__global__ __launch_bounds__(64) void k_sim_lane(SimArgs a, int act) {
+  extern __shared__ double lds_h[];
+  const InstDev& I = a.inst[0];
+  const int lane = threadIdx.x;
+  const int64_t blk = blockIdx.x;
+  const int64_t p = blk * 64 + lane;
+  const bool valid = p < I.N;
+  const int64_t gp = I.path_offset + p;
+  const uint32_t tag = (uint32_t)I.tag;
+  const int M = I.M, m = a.m;
+  constexpr bool F64 = sizeof(T) == 8;
+  T xs[kMaxM], ls[kMaxM], A[kMaxM], B[kMaxM];
+#pragma unroll
+  for (int j = 0; j < kMaxM; ++j) {
+    xs[j] = F64 ? (T)a.xd[j] : (T)a.xs[j];
+    ls[j] = F64 ? (T)a.ld[j] : (T)a.ls[j];
+    A[j] = (T)I.A[j];
+    B[j] = (T)I.B[j];
+  }
+  T Y = F64 ? (T)I.Y0 : (T)I.Y0_f;
+  long long clamped = 0, ood = 0;
+  for (int i0 = 0; i0 < M; i0 += 4) {
+    const u32x4 r = philox_step_quad(a.seed, (uint32_t)(i0 >> 2), gp, tag);
+    T xq[4];
+    if constexpr (F64) normals4_f64(r, xq); else normals4_f32(r, xq);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (i0 + u < M) {
+        T y[kMaxM];
+        if constexpr (NET) {
+          if (Y < I.dom_lo || Y > I.dom_hi) ++ood;
+          net_lane_f64((const double*)a.wpack, I.c0d, (double)Y, m, act, lds_h + lane,
+                       lds_h + 64 * 64 + lane, (double*)y);
+        } else {
+#pragma unroll
+          for (int j = 0; j < kMaxM; ++j) y[j] = A[j] * Y + B[j];
+        }
+        Y = bary_lane<T>(xs, ls, m, y, xq[u]);
+        if (I.clamp_zero && Y < T(0)) { Y = T(0); ++clamped; }
+      }
+    }
+  }
+  if (a.YT && valid) ((T*)a.YT)[I.yt_offset + p] = Y;
+  const double f0 = valid ? (double)Y : 0.0;
+  const double f1 = valid ? fmax((double)Y - I.K, 0.0) : 0.0;
+  block_partial(f0, f1, valid ? clamped : 0, valid ? ood : 0, a.partials + I.part_offset + blk);
+}
+
+hipError_t launch_sim_lane(int prec, int use_net, int act, const SimArgs& a, int64_t n_blocks,
+                           hipStream_t s) {
+  if (n_blocks <= 0) return hipSuccess;
+  dim3 grid((unsigned)n_blocks), block(64);
+  if (prec == SL7_F64) {
+    if (use_net) {
+      const size_t lds = 2 * 64 * 64 * sizeof(double);
+      hipLaunchKernelGGL((k_sim_lane<double, true>), grid, block, lds, s, a, act);
+    } else {
+      hipLaunchKernelGGL((k_sim_lane<double, false>), grid, block, 0, s, a, act);
+    }
+  } else {
+    hipLaunchKernelGGL((k_sim_lane<float, false>), grid, block, 0, s, a, act);
+  }
+  return hipGetLastError();
+}
+
+// Final per-instance statistics: one workgroup per instance sums its block
+// partials in a fixed order (strided per thread, Neumaier-compensated), then
+// combines the 256 thread sums in a fixed tree.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+struct Comp {
+  double s, c;
+  __device__ void add(double v) {
+    double t, e;
+    two_sum(s, v, t, e);
+    s = t;
+    c += e;
+  }
+  __device__ void merge(const Comp& o) {
+    double t, e;
+    two_sum(s, o.s, t, e);
+    s = t;
+    c += o.c + e;
+  }
+  __device__ double value() const { return s + c; }
+};
+
+__global__ __launch_bounds__(256) void k_finalize(const Partial* __restrict__ parts,
+                                                  const InstDev* __restrict__ inst,
+                                                  sl7_stats* __restrict__ out) {
+  const InstDev& I = inst[blockIdx.x];
+  const int64_t nb = (I.N + 63) / 64;
+  const Partial* P = parts + I.part_offset;
+  Comp acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  long long cl = 0, od = 0;
+  for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
+    const Partial q = P[b];
+    acc[0].add(q.s[0]); acc[1].add(q.s[1]); acc[2].add(q.q[0]); acc[3].add(q.q[1]);
+    cl += q.clamped; od += q.ood;
+  }
+  __shared__ Comp sh[4][256];
+  __shared__ long long shl[2][256];
+  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
+  shl[0][threadIdx.x] = cl;
+  shl[1][threadIdx.x] = od;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x].merge(sh[k][threadIdx.x + w]);
+      shl[0][threadIdx.x] += shl[0][threadIdx.x + w];
+      shl[1][threadIdx.x] += shl[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    sl7_stats st;
+    const double n = (double)I.N;
+    for (int k = 0; k < 2; ++k) {
+      const double S = sh[k][0].value(), Q = sh[2 + k][0].value();
+      st.mean[k] = S / n;
+      st.var[k] = I.N > 1 ? fmax(Q - S * (S / n), 0.0) / (n - 1.0) : 0.0;
+      st.se[k] = sqrt(st.var[k] / n);
+    }
+    st.n = I.N;
+    st.n_clamped = shl[0][0];
+    st.n_out_of_domain = shl[1][0];
+    st.reserved = 0;
+    out[blockIdx.x] = st;
+  }
+}
+
+hipError_t launch_finalize(const Partial* parts, const InstDev* inst, int n_inst, sl7_stats* out,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(n_inst), dim3(256), 0, s, parts, inst, out);
+  return hipGetLastError();
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
+  return hipGetLastError();
+}
+
+// Batched network evaluation in double, one input row per lane: h0 = in_scale
+// * in + in_shift, then the layers exactly as in eq. (6.3)/(6.4).  w0full:
+// [in_scale (d_in), in_shift (d_in), W0 (64 x d_in), b0 (64)], net: the lane
+// layout above (its wY part unused here).
+__global__ __launch_bounds__(64) void k_eval_lane(const double* __restrict__ net,
+                                                  const double* __restrict__ w0full, int d_in,
+                                                  int m, int act, const float* __restrict__ in,
+                                                  int64_t B, float* __restrict__ out) {
+  extern __shared__ double lds_h[];
+  const int lane = threadIdx.x;
+  const int64_t row = (int64_t)blockIdx.x * 64 + lane;
+  const bool valid = row < B;
+  double h0[kMaxDinLane];
+  for (int k = 0; k < kMaxDinLane; ++k) h0[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < kMaxDinLane; ++k)
+    if (k < d_in) h0[k] = valid ? w0full[k] * (double)in[row * d_in + k] + w0full[d_in + k] : 0.0;
+  const double* W0 = w0full + 2 * d_in;
+  const double* b0 = W0 + 64 * d_in;
+  double* hA = lds_h + lane;
+  double* hB = lds_h + 64 * 64 + lane;
+  for (int o = 0; o < 64; ++o) {
+    double s = b0[o];
+#pragma unroll
+    for (int k = 0; k < kMaxDinLane; ++k)
+      if (k < d_in) s = fma(W0[o * d_in + k], h0[k], s);
+    hA[o * 64] = act_fn(act, s);
+  }
+  const double* Wl = net + 64;
+  double* hin = hA;
+  double* hout = hB;
+  for (int l = 0; l < 3; ++l) {
+    const double* bl = Wl + 64 * 64;
+    for (int o = 0; o < 64; ++o) {
+      double s = bl[o];
+      const double* r = Wl + o * 64;
+      for (int k = 0; k < 64; ++k) s = fma(r[k], hin[k * 64], s);
+      hout[o * 64] = act_fn(act, s);
+    }
+    Wl += 64 * 64 + 64;
+    double* t = hin; hin = hout; hout = t;
+  }
+  const double* bh = Wl + 64 * m;
+  for (int j = 0; j < m; ++j) {
+    double s = bh[j];
+    const double* r = Wl + j * 64;
+    for (int k = 0; k < 64; ++k) s = fma(r[k], hin[k * 64], s);
+    if (valid) out[row * m + j] = (float)s;
+  }
+}
+
+hipError_t launch_eval_lane(const double* net, const double* w0full, int d_in, int m, int act,
+                            const float* in, int64_t B, float* out, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  const size_t lds = 2 * 64 * 64 * sizeof(double);
+  hipLaunchKernelGGL(k_eval_lane, dim3((unsigned)((B + 63) / 64)), dim3(64), lds, s, net, w0full,
+                     d_in, m, act, in, B, out);
+  return hipGetLastError();
+}
+
+}  // namespace sl7

@@ -1,0 +1,450 @@
+// Fused Seven-League step on MFMA (gfx950): FP32, BF16 and FP16 network
+// GEMMs, FP32 interpolation and state, FP64 block sums.
+//
+// One wave64 advances a group of 16 paths at a time.  The network H
+// (eq. 6.3/6.4) runs with the paths in the N dimension of 16x16 MFMA tiles
+// and the weights as the A operand, so a layer's accumulator tile (lane
+// (g, n): path n, units 4g..4g+3 of each 16-unit block) is, after bias
+// (folded into the accumulator input), ReLU and conversion, directly the B
+// operand of the next layer; the host permutes the weight columns to match.
+// All weights stay in registers for the life of the wave.
+//
+// Per step (Algorithm I, steps 3-6):
+//   layer 1   z = ReLU(Y w_Y + c)       rank one in Y, VALU FP32 (c folds dt, theta)
+//   layers 2-4 z = ReLU(W z + b)        MFMA, operands FP32/BF16/FP16, FP32 accumulate
+//   head      y = W z + b               MFMA, rows 4g..4g+3 of the m outputs
+//   g_m(X)    barycentric (second form): each lane sums t_j y_j and t_j over
+//             its rows, two xor-shuffles complete the sums for the path.
+// Normals: each of the four lane groups draws one Philox quad (four steps) of
+// the path, so one Philox call per lane covers 16 steps; a shuffle hands the
+// step's normal to all four lanes of the path.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+
+namespace sl7 {
+
+// ------------------------------------------------------------------------
+// BF16 / FP16 operands (v_mfma_f32_16x16x32_{bf16,f16}).
+// ------------------------------------------------------------------------
+template <int P>
+struct H16;
+
+template <>
+struct H16<SL7_BF16> {
+  typedef bf16x8 v8;
+  static __device__ __forceinline__ f32x4 mfma(v8 a, v8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  // RNE conversion of two floats, then ReLU on the packed halves: a negative
+  // value has its sign bit set, so a signed 16-bit max with 0 clears it.
+  static __device__ __forceinline__ uint32_t pack_relu(float x, float y) {
+    const bf16x2 h = __builtin_convertvector((f32x2){x, y}, bf16x2);
+    const s16x2 s = __builtin_elementwise_max(__builtin_bit_cast(s16x2, h), (s16x2){0, 0});
+    return __builtin_bit_cast(uint32_t, s);
+  }
+};
+
+template <>
+struct H16<SL7_F16> {
+  typedef f16x8 v8;
+  static __device__ __forceinline__ f32x4 mfma(v8 a, v8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ uint32_t pack_relu(float x, float y) {
+    const f16x2 h = __builtin_convertvector((f32x2){x, y}, f16x2);
+    const s16x2 s = __builtin_elementwise_max(__builtin_bit_cast(s16x2, h), (s16x2){0, 0});
+    return __builtin_bit_cast(uint32_t, s);
+  }
+};
+
+// Eight activations (units 4g..4g+3 of two consecutive 16-unit blocks) as
+// one K=32 B operand.
+template <int P>
+__device__ __forceinline__ typename H16<P>::v8 pack8(f32x4 lo, f32x4 hi) {
+  const u32x4 w = {H16<P>::pack_relu(lo[0], lo[1]), H16<P>::pack_relu(lo[2], lo[3]),
+                   H16<P>::pack_relu(hi[0], hi[1]), H16<P>::pack_relu(hi[2], hi[3])};
+  return __builtin_bit_cast(typename H16<P>::v8, w);
+}
+
+template <int P>
+struct NetRegsH {
+  typedef typename H16<P>::v8 v8;
+  v8 A[3][4][2];  // hidden layers: [layer][out block][K block]
+  v8 Ah[2];       // head: [K block]
+  f32x4 C[3][4];  // hidden biases (accumulator input)
+  f32x4 Ch;       // head bias
+  f32x4 wY[4];    // first-layer weight of Y (times its input scale)
+
+  __device__ __forceinline__ void load(const u32x4* __restrict__ wp, int lane) {
+    int s = 0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) A[l][b][c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) Ah[c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) C[l][b] = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
+    Ch = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) wY[b] = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
+  }
+};
+
+template <int P>
+__device__ __forceinline__ f32x4 chain_h(const NetRegsH<P>& R, typename H16<P>::v8 B0,
+                                         typename H16<P>::v8 B1) {
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    f32x4 acc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = H16<P>::mfma(R.A[l][b][0], B0, R.C[l][b]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = H16<P>::mfma(R.A[l][b][1], B1, acc[b]);
+    B0 = pack8<P>(acc[0], acc[1]);
+    B1 = pack8<P>(acc[2], acc[3]);
+  }
+  f32x4 y = H16<P>::mfma(R.Ah[0], B0, R.Ch);
+  return H16<P>::mfma(R.Ah[1], B1, y);
+}
+
+// ------------------------------------------------------------------------
+// FP32 operands (v_mfma_f32_16x16x4_f32): K block kb = 4 b_in + r takes
+// register r of block b_in of the previous layer's accumulator.
+// ------------------------------------------------------------------------
+struct NetRegsF {
+  float A[3][4][16];
+  float Ah[16];
+  f32x4 C[3][4];
+  f32x4 Ch;
+  f32x4 wY[4];
+
+  __device__ __forceinline__ void load(const u32x4* __restrict__ wp, int lane) {
+    int s = 0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const f32x4 v = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) A[l][b][4 * q + e] = v[e];
+        }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f32x4 v = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Ah[4 * q + e] = v[e];
+    }
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) C[l][b] = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
+    Ch = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) wY[b] = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
+  }
+};
+
+__device__ __forceinline__ f32x4 relu4(f32x4 v) {
+  return (f32x4){fmaxf(v[0], 0.f), fmaxf(v[1], 0.f), fmaxf(v[2], 0.f), fmaxf(v[3], 0.f)};
+}
+
+__device__ __forceinline__ f32x4 chain_f(const NetRegsF& R, f32x4 Bv[4]) {
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    f32x4 acc[4] = {R.C[l][0], R.C[l][1], R.C[l][2], R.C[l][3]};
+#pragma unroll
+    for (int kb = 0; kb < 16; ++kb)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(R.A[l][b][kb], Bv[kb >> 2][kb & 3], acc[b],
+                                                      0, 0, 0);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) Bv[b] = relu4(acc[b]);
+  }
+  f32x4 y = R.Ch;
+#pragma unroll
+  for (int kb = 0; kb < 16; ++kb)
+    y = __builtin_amdgcn_mfma_f32_16x16x4f32(R.Ah[kb], Bv[kb >> 2][kb & 3], y, 0, 0, 0);
+  return y;
+}
+
+// ------------------------------------------------------------------------
+// Barycentric interpolation over the lane's rows 4g..4g+3 of the head tile.
+// xr/lr: this lane's nodes and weights (1e30 / 0 for rows >= m).
+// ------------------------------------------------------------------------
+__device__ __forceinline__ float interp_rows(float X, f32x4 yv, const float xr[4],
+                                             const float lr[4], const SimArgs& a, int m) {
+  bool anyhit = false;
+#pragma unroll
+  for (int j = 0; j < kMaxM; ++j)
+    if (j < m && X == a.xs[j]) anyhit = true;
+  float num = 0.f, den = 0.f, yh = 0.f;
+  bool own = false;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const float t = lr[r] * fast_rcp(X - xr[r]);
+    num = fmaf(t, yv[r], num);
+    den += t;
+    if (X == xr[r]) { own = true; yh = yv[r]; }
+  }
+  if (anyhit) {
+    num = own ? yh : 0.f;
+    den = own ? 1.f : 0.f;
+  }
+  num += __shfl_xor(num, 16);
+  den += __shfl_xor(den, 16);
+  num += __shfl_xor(num, 32);
+  den += __shfl_xor(den, 32);
+  return num / den;
+}
+
+__device__ __forceinline__ void lane_rows(const SimArgs& a, int m, int g, float xr[4],
+                                          float lr[4]) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    xr[r] = 1e30f;
+    lr[r] = 0.f;
+#pragma unroll
+    for (int j = 0; j < kMaxM; ++j)
+      if (j < m && j == 4 * g + r) {
+        xr[r] = a.xs[j];
+        lr[r] = a.ls[j];
+      }
+  }
+}
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Next work item range [item, end) for this wave, or item >= n_items.
+__device__ __forceinline__ uint64_t grab_items(const SimArgs& a, int lane) {
+  unsigned long long it = 0;
+  if (lane == 0) it = atomicAdd(a.counter, (unsigned long long)a.grab);
+  return uniform_u64(__shfl(it, 0));
+}
+
+__device__ __forceinline__ const InstDev* locate(const SimArgs& a, uint64_t item, int64_t& blk) {
+  int lo = 0, hi = a.n_order;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((uint64_t)a.item_prefix[mid] <= item) lo = mid; else hi = mid;
+  }
+  blk = (int64_t)item - a.item_prefix[lo];
+  return a.inst + a.order[lo];
+}
+
+// One 64-path block: four groups of 16 paths, each for all M steps.  Lane
+// (g = t, n) keeps Y_T of path 16 t + n, so afterwards lane l holds path l of
+// the block, the layout of the fixed-order block reduction.
+template <class Net>
+__device__ __forceinline__ void sim_block(const SimArgs& a, const InstDev& I, int64_t blk,
+                                          const Net& net, const float xr[4], const float lr[4],
+                                          int lane, int g, int n) {
+  const int M = I.M;
+  const int m = a.m;
+  const uint32_t tag = (uint32_t)I.tag;
+  const bool clamp = I.clamp_zero != 0;
+  const double dlo = I.dom_lo, dhi = I.dom_hi;
+  f32x4 c0[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) c0[b] = *(const f32x4*)(I.c0 + 16 * b + 4 * g);
+  float Yrec = 0.f;
+  long long clamped = 0, ood = 0;
+  for (int t = 0; t < 4; ++t) {
+    const int64_t gp = I.path_offset + blk * 64 + 16 * t + n;
+    float Y = I.Y0_f;
+    float xc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int i0 = 0; i0 < M; i0 += 4) {
+      if ((i0 & 15) == 0) {
+        const u32x4 r = philox_step_quad(a.seed, (uint32_t)(i0 >> 2) + (uint32_t)g, gp, tag);
+        normals4_f32(r, xc);
+      }
+      const int src = n + 16 * ((i0 >> 2) & 3);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (i0 + u < M) {
+          const float X = __shfl(xc[u], src);
+          if (g == t && ((double)Y < dlo || (double)Y > dhi)) ++ood;
+          const f32x4 yv = net.eval(Y, c0);
+          Y = interp_rows(X, yv, xr, lr, a, m);
+          if (clamp && Y < 0.f) {
+            Y = 0.f;
+            if (g == t) ++clamped;
+          }
+        }
+      }
+    }
+    if (g == t) Yrec = Y;
+  }
+  const int64_t pl = blk * 64 + lane;
+  const bool valid = pl < I.N;
+  if (a.YT && valid) ((float*)a.YT)[I.yt_offset + pl] = Yrec;
+  const double f0 = valid ? (double)Yrec : 0.0;
+  const double f1 = valid ? fmax((double)Yrec - I.K, 0.0) : 0.0;
+  block_partial(f0, f1, valid ? clamped : 0, valid ? ood : 0, a.partials + I.part_offset + blk);
+}
+
+template <int P>
+struct NetH {
+  NetRegsH<P> R;
+  __device__ __forceinline__ f32x4 eval(float Y, const f32x4 c0[4]) const {
+    f32x4 z[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) z[b][r] = fmaf(Y, R.wY[b][r], c0[b][r]);
+    return chain_h<P>(R, pack8<P>(z[0], z[1]), pack8<P>(z[2], z[3]));
+  }
+};
+
+struct NetF {
+  NetRegsF R;
+  __device__ __forceinline__ f32x4 eval(float Y, const f32x4 c0[4]) const {
+    f32x4 Bv[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Bv[b][r] = fmaxf(fmaf(Y, R.wY[b][r], c0[b][r]), 0.f);
+    return chain_f(R, Bv);
+  }
+};
+
+template <class Net>
+__device__ __forceinline__ void sim_persistent(const SimArgs& a, const Net& net) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+  float xr[4], lr[4];
+  lane_rows(a, a.m, g, xr, lr);
+  for (;;) {
+    const uint64_t item0 = grab_items(a, lane);
+    if (item0 >= (uint64_t)a.n_items) break;
+    const uint64_t end = min(item0 + (uint64_t)a.grab, (uint64_t)a.n_items);
+    for (uint64_t item = item0; item < end; ++item) {
+      int64_t blk;
+      const InstDev* I = locate(a, item, blk);
+      sim_block(a, *I, blk, net, xr, lr, lane, g, n);
+    }
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_sim_mfma_h(SimArgs a) {
+  NetH<P> net;
+  net.R.load((const u32x4*)a.wpack, threadIdx.x & 63);
+  sim_persistent(a, net);
+}
+
+__global__ __launch_bounds__(256) void k_sim_mfma_f(SimArgs a) {
+  NetF net;
+  net.R.load((const u32x4*)a.wpack, threadIdx.x & 63);
+  sim_persistent(a, net);
+}
+
+hipError_t launch_sim_mfma(int prec, const SimArgs& a, int grid, int waves_per_block,
+                           hipStream_t s) {
+  dim3 g(grid), b(64 * waves_per_block);
+  if (prec == SL7_BF16) hipLaunchKernelGGL(k_sim_mfma_h<SL7_BF16>, g, b, 0, s, a);
+  else if (prec == SL7_F16) hipLaunchKernelGGL(k_sim_mfma_h<SL7_F16>, g, b, 0, s, a);
+  else hipLaunchKernelGGL(k_sim_mfma_f, g, b, 0, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// Batched network evaluation (eq. 6.4) on the same MFMA chain: 16 rows per
+// wave pass; the first layer is a full d_in-wide product in FP32.
+// w0n: [64 x d_in] first-layer weights times input scales; c0n: [64] the
+// shift and bias folded.
+// ------------------------------------------------------------------------
+template <class Net>
+__device__ __forceinline__ void eval_rows(const Net& net, const float* __restrict__ w0n,
+                                          const float* __restrict__ c0n, int d_in, int m,
+                                          const float* __restrict__ in, int64_t B,
+                                          float* __restrict__ out) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t grp = wave; grp * 16 < B; grp += nwaves) {
+    const int64_t row = grp * 16 + n;
+    const bool valid = row < B;
+    float x[kMaxDinLane];
+#pragma unroll
+    for (int k = 0; k < kMaxDinLane; ++k) x[k] = (valid && k < d_in) ? in[row * d_in + k] : 0.f;
+    f32x4 z[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = 16 * b + 4 * g + r;
+        float s = c0n[o];
+#pragma unroll
+        for (int k = 0; k < kMaxDinLane; ++k)
+          if (k < d_in) s = fmaf(w0n[o * d_in + k], x[k], s);
+        z[b][r] = s;
+      }
+    const f32x4 y = net.eval_z0(z);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = 4 * g + r;
+      if (valid && j < m) out[row * m + j] = y[r];
+    }
+  }
+}
+
+template <int P>
+struct NetHz : NetH<P> {
+  __device__ __forceinline__ f32x4 eval_z0(const f32x4 z[4]) const {
+    return chain_h<P>(this->R, pack8<P>(z[0], z[1]), pack8<P>(z[2], z[3]));
+  }
+};
+
+struct NetFz : NetF {
+  __device__ __forceinline__ f32x4 eval_z0(const f32x4 z[4]) const {
+    f32x4 Bv[4] = {relu4(z[0]), relu4(z[1]), relu4(z[2]), relu4(z[3])};
+    return chain_f(R, Bv);
+  }
+};
+
+template <int P>
+__global__ __launch_bounds__(256) void k_eval_mfma_h(const void* wpack, const float* w0n,
+                                                     const float* c0n, int d_in, int m,
+                                                     const float* in, int64_t B, float* out) {
+  NetHz<P> net;
+  net.R.load((const u32x4*)wpack, threadIdx.x & 63);
+  eval_rows(net, w0n, c0n, d_in, m, in, B, out);
+}
+
+__global__ __launch_bounds__(256) void k_eval_mfma_f(const void* wpack, const float* w0n,
+                                                     const float* c0n, int d_in, int m,
+                                                     const float* in, int64_t B, float* out) {
+  NetFz net;
+  net.R.load((const u32x4*)wpack, threadIdx.x & 63);
+  eval_rows(net, w0n, c0n, d_in, m, in, B, out);
+}
+
+hipError_t launch_eval_mfma(int prec, const void* wpack, const float* w0n, const float* c0n,
+                            int d_in, int m, const float* in, int64_t B, float* out,
+                            hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  const int64_t groups = (B + 15) / 16;
+  const int grid = (int)std::min<int64_t>((groups + 3) / 4, 2048);
+  if (prec == SL7_BF16)
+    hipLaunchKernelGGL(k_eval_mfma_h<SL7_BF16>, dim3(grid), dim3(256), 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
+  else if (prec == SL7_F16)
+    hipLaunchKernelGGL(k_eval_mfma_h<SL7_F16>, dim3(grid), dim3(256), 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
+  else
+    hipLaunchKernelGGL(k_eval_mfma_f, dim3(grid), dim3(256), 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
+  return hipGetLastError();
+}
+
+}  // namespace sl7

@@ -1,0 +1,79 @@
+// Host-side internals of the Seven-League library: error helpers, device
+// buffers, per-device workspaces and the network handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sl7_internal.hpp"
+
+namespace sl7 {
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+int n_theta(int model);
+int current_device(int* dev);
+int gh_nodes(int m, double* x, double* w);
+
+// A device allocation that only grows.  `generation` changes whenever the
+// address changes (captured graphs keyed on it must be rebuilt).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  uint64_t generation = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf();
+  int reserve(size_t n);
+};
+
+// Scratch of one device, shared by the calls made on it (serialised by mu).
+struct Workspace {
+  std::mutex mu;
+  int n_cu = 0;
+  DevBuf inst, prefix, order, counter, partials, stats;
+  DevBuf aux[8];  // adjoint checkpoints, trainer buffers, ...
+  sl7_stats* stats_host = nullptr;
+  int stats_host_n = 0;
+  int stats_host_reserve(int n);
+};
+
+Workspace& workspace(int dev);
+
+// The network handle behind sl7_mlp.
+struct Mlp {
+  sl7_mlp_desc d;
+  std::vector<float> params;
+  std::vector<int64_t> W_off, b_off;
+  std::string meta;
+  std::mutex mu;
+  int device = -1;
+  std::unique_ptr<DevBuf> pack[4];  // MFMA register layouts, by precision
+  std::unique_ptr<DevBuf> net64, w0full, w0n, c0n;
+
+  void layout();
+  float W(int l, int o, int k) const;
+  float b(int l, int o) const;
+  void drop_device();
+  int ensure_device(int prec);
+};
+
+int64_t n_params_of(const sl7_mlp_desc& d);
+int check_desc(const sl7_mlp_desc* d);
+int check_problem(const sl7_problem* pr, const Mlp* H, int prec, const char* name);
+int check_plan(const sl7_plan* p);
+int default_plan(int prec, sl7_plan* p);
+int prepare_instances(const sl7_problem* prs, int n, const Mlp* H, int prec, uint64_t seed,
+                      void* YT_dev, hipStream_t stream, Workspace& ws, SimArgs& a);
+int launch_instances(const SimArgs& a, int n, int64_t N0, const Mlp* H, int prec,
+                     const sl7_plan& plan, hipStream_t stream, Workspace& ws);
+int run_instances(const sl7_problem* prs, int n, const Mlp* H, int prec, uint64_t seed,
+                  void* YT_dev, const sl7_plan* plan, hipStream_t stream, Workspace& ws);
+int fetch_stats(Workspace& ws, int n, sl7_stats* out, hipStream_t stream);
+
+}  // namespace sl7

@@ -1,0 +1,140 @@
+"""CPU-side checks of the C ABI: every declared symbol is exported, host logic
+(Gauss-Hermite nodes, weight file, argument validation) behaves as the
+header states.  No GPU work is launched here."""
+import ctypes
+import os
+import re
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sl7.h")
+WEIGHTS = os.path.join(ROOT, "tests", "golden", "gbm_mlp_4x64.sl7w")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2302_05170_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sl7_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 10
+    missing = [n for n in names if not hasattr(L.lib(), n)]
+    assert not missing, missing
+
+
+def test_version_and_error_string(L):
+    assert b"gfx950" in L.lib().sl7_version()
+    assert L.lib().sl7_gh_nodes(0, None, None) == L.SL7_EINVAL
+    assert b"m=0" in L.lib().sl7_last_error()
+
+
+@pytest.mark.parametrize("m", range(1, 17))
+def test_gh_nodes_match_oracle(L, m):
+    import paper_2302_05170_amd as S
+    x, w = S.gh_nodes(m)
+    xo, wo = oracle.gh_nodes(m)
+    assert np.max(np.abs(x - xo)) <= 1e-13 * max(1.0, np.max(np.abs(xo)))
+    assert np.max(np.abs(w - wo)) <= 1e-13
+    if m % 2:
+        assert x[m // 2] == 0.0
+
+
+def test_weight_file_read_by_both_sides(L):
+    import paper_2302_05170_amd as S
+    H = S.Mlp.load(WEIGHTS)
+    Ho = oracle.load_mlp(WEIGHTS)
+    d = H.desc()
+    assert (d.d_in, d.width, d.depth, d.m, d.act, d.model) == (Ho.d_in, Ho.width, Ho.depth, Ho.m,
+                                                               Ho.act, Ho.model)
+    assert np.array_equal(H.params(), Ho.params_f32())
+    assert [d.in_scale[k] for k in range(4)] == list(Ho.in_scale)
+    with tempfile.TemporaryDirectory() as tmp:
+        p = os.path.join(tmp, "copy.sl7w")
+        H.save(p)
+        assert open(p, "rb").read() == open(WEIGHTS, "rb").read()
+
+
+def test_bad_weight_files(L):
+    import paper_2302_05170_amd as S
+    with tempfile.TemporaryDirectory() as tmp:
+        p = os.path.join(tmp, "bad.sl7w")
+        open(p, "wb").write(b"NOPE" + bytes(64))
+        with pytest.raises(S.Sl7Error) as e:
+            S.Mlp.load(p)
+        assert e.value.code == L.SL7_EINVAL
+        open(p, "wb").write(open(WEIGHTS, "rb").read()[:200])
+        with pytest.raises(S.Sl7Error) as e:
+            S.Mlp.load(p)
+        assert e.value.code == L.SL7_EINVAL
+        with pytest.raises(S.Sl7Error) as e:
+            S.Mlp.load(os.path.join(tmp, "missing.sl7w"))
+        assert e.value.code == L.SL7_EIO
+
+
+def test_create_rejects_nonfinite_and_bad_shapes(L):
+    import paper_2302_05170_amd as S
+    p = W.glorot_params(4, 5, seed=1)
+    args = (4, 5, W.GBM)
+    aff = ([1.0] * 4, [0.0] * 4, W.GBM_DOMAIN_LO, W.GBM_DOMAIN_HI)
+    S.Mlp.create(*args, p, *aff)
+    bad = p.copy()
+    bad[17] = np.nan
+    with pytest.raises(S.Sl7Error) as e:
+        S.Mlp.create(*args, bad, *aff)
+    assert e.value.code == L.SL7_ENUMERIC
+    with pytest.raises(S.Sl7Error) as e:
+        S.Mlp.create(4, 9, W.GBM, W.glorot_params(4, 9), *aff)  # m > 8
+    assert e.value.code == L.SL7_EINVAL
+
+
+def _sim_rc(L, H=None, prec=1, **kw):
+    import paper_2302_05170_amd as S
+    base = dict(model=W.GBM, theta=(0.3, 0.1), Y0=1.0, T=1.0, M=4, m=5, N=100)
+    base.update(kw)
+    pr = S.Problem(**base).c()
+    st = L.Stats()
+    rc = L.lib().sl7_simulate(ctypes.byref(pr), H.handle if H else None, prec, 42, None,
+                              ctypes.byref(st), None, None)
+    return rc, L.lib().sl7_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(m=1), "m=1"), (dict(m=9), "m=9"), (dict(M=0), "M=0"), (dict(N=0), "N=0"),
+    (dict(T=0.0), "T"), (dict(T=float("nan")), "T"), (dict(theta=(-0.1, 0.1)), "sigma"),
+    (dict(Y0=float("inf")), "Y0"), (dict(model=7), "model"),
+    (dict(model=W.CIR, theta=(1.0, 0.05, 0.2), Y0=-0.1), "Y0"),
+    (dict(model=W.OU, theta=(0.5, 0.3, 0.0)), "lambda"),
+])
+def test_simulate_rejects_bad_problems(L, kw, needle):
+    rc, msg = _sim_rc(L, **kw)
+    assert rc == L.SL7_EINVAL and needle in msg, (rc, msg)
+
+
+def test_simulate_rejects_mismatched_network_and_precision(L):
+    import paper_2302_05170_amd as S
+    H = S.Mlp.load(WEIGHTS)
+    rc, msg = _sim_rc(L, H=H, m=7)
+    assert rc == L.SL7_EINVAL and "m=7" in msg
+    rc, msg = _sim_rc(L, H=H, model=W.OU, theta=(0.5, 0.3, 1.0))
+    assert rc == L.SL7_EINVAL
+    rc, msg = _sim_rc(L, prec=L.BF16)  # analytic map has no BF16 form
+    assert rc == L.SL7_EUNSUPPORTED
+    rc, msg = _sim_rc(L, model=W.CIR, theta=(1.0, 0.05, 0.2), Y0=0.05, m=5)
+    assert rc == L.SL7_EUNSUPPORTED
+    rc, msg = _sim_rc(L, prec=9)
+    assert rc == L.SL7_EINVAL

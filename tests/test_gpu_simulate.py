@@ -1,0 +1,207 @@
+"""GPU parity of the fused online stage (Algorithm I, steps 2-8) against the
+FP64 oracle, through the C ABI.
+
+Tolerances: per-path Y_T relative error max over the compared paths, 1e-12
+in FP64, 1e-5 in FP32, 2e-3 in BF16 (5e-4 in FP16); path means 1e-6 relative
+in FP32.  rel = |gpu - oracle| / max(|oracle|, 1e-12).
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+WEIGHTS = os.path.join(ROOT, "tests", "golden", "gbm_mlp_4x64.sl7w")
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-3, "f16": 5e-4}
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_2302_05170_amd as S
+    assert torch.cuda.is_available()
+    return S
+
+
+@pytest.fixture(scope="module")
+def H(S):
+    return S.Mlp.load(WEIGHTS)
+
+
+@pytest.fixture(scope="module")
+def Ho():
+    return oracle.load_mlp(WEIGHTS)
+
+
+def rel(got, ref):
+    return np.abs(got - ref) / np.maximum(np.abs(ref), 1e-12)
+
+
+def gpu_yt(S, pr, H, prec, seed, plan=None):
+    st, yt = S.simulate(pr, H, prec=prec, seed=seed, want_yt=True, plan=plan)
+    torch.cuda.synchronize()
+    return st, yt.double().cpu().numpy()
+
+
+def orc(pr, Ho, seed, paths):
+    opr = oracle.Problem(pr.model, pr.theta, pr.Y0, pr.T, pr.M, pr.m, pr.instance)
+    y, ncl, nood = oracle.simulate(opr, Ho, seed, paths)
+    return y
+
+
+def test_c0_f64_analytic_all_paths(S):
+    c = W.CONFIGS["c0"]
+    pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
+    st, y = gpu_yt(S, pr, None, "f64", c["seed"])
+    ref = orc(pr, None, c["seed"], np.arange(c["N"]))
+    print("c0 f64 max rel", rel(y, ref).max())
+    assert rel(y, ref).max() <= TOL["f64"]
+    for k, f in enumerate(oracle.payoffs(ref, c["K"])):
+        e = oracle.estimate(f)
+        assert abs(st["mean"][k] - e["mean"]) <= 1e-12 * abs(e["mean"])
+        assert abs(st["var"][k] - e["var"]) <= 1e-9 * e["var"]
+        assert abs(st["se"][k] - e["se"]) <= 1e-9 * e["se"]
+    assert st["n"] == c["N"]
+
+
+def test_c0_f32_analytic_all_paths(S):
+    c = W.CONFIGS["c0"]
+    pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
+    st, y = gpu_yt(S, pr, None, "f32", c["seed"])
+    ref = orc(pr, None, c["seed"], np.arange(c["N"]))
+    r = rel(y, ref)
+    print("c0 f32 max rel", r.max(), "p99", np.quantile(r, 0.99))
+    assert r.max() <= TOL["f32"]
+    for k, f in enumerate(oracle.payoffs(ref, c["K"])):
+        e = oracle.estimate(f)
+        assert abs(st["mean"][k] - e["mean"]) <= 1e-6 * abs(e["mean"])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_ou_analytic(S, prec):
+    pr = S.Problem(W.OU, (0.5, 0.4, 1.7), 0.2, 2.0, 8, 5, 10_000, K=0.4, instance=3)
+    st, y = gpu_yt(S, pr, None, prec, 9)
+    ref = orc(pr, None, 9, np.arange(pr.N))
+    # OU paths cross zero: compare against the path scale instead of |Y|
+    err = np.abs(y - ref) / np.maximum(np.abs(ref), 0.5)
+    assert err.max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("m", [2, 3, 4, 6, 7, 8])
+def test_analytic_every_m_and_ragged_M(S, m):
+    pr = S.Problem(W.GBM, (0.25, 0.05), 1.3, 0.7, 5, m, 3001, K=1.2)
+    for prec in ("f64", "f32"):
+        st, y = gpu_yt(S, pr, None, prec, 1234)
+        ref = orc(pr, None, 1234, np.arange(pr.N))
+        assert rel(y, ref).max() <= TOL[prec], (m, prec)
+
+
+@pytest.mark.parametrize("N", [1, 15, 63, 65, 1000, 4099])
+def test_ragged_path_counts(S, H, Ho, N):
+    c = W.CONFIGS["c1"]
+    pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 7, c["m"], N, K=c["K"])
+    ref = orc(pr, Ho, 5, np.arange(N))
+    for prec in ("f64", "f32", "bf16", "f16"):
+        st, y = gpu_yt(S, pr, H, prec, 5)
+        assert st["n"] == N
+        assert rel(y, ref).max() <= TOL[prec], (N, prec)
+        assert abs(st["mean"][0] - y.mean()) <= 1e-12 * abs(y.mean()) + 1e-7
+
+
+def test_mlp_f64_matches_oracle(S, H, Ho):
+    c = W.CONFIGS["c1"]
+    pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], 4096, K=c["K"])
+    st, y = gpu_yt(S, pr, H, "f64", c["seed"])
+    ref = orc(pr, Ho, c["seed"], np.arange(pr.N))
+    assert rel(y, ref).max() <= TOL["f64"]
+    opr = oracle.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"])
+    _, _, nood = oracle.simulate(opr, Ho, c["seed"], np.arange(pr.N))
+    assert st["n_out_of_domain"] == nood
+
+
+def test_mlp_f32_paths_and_means(S, H, Ho):
+    """C1 setting on 2^17 paths: every path and both payoff means."""
+    c = W.CONFIGS["c1"]
+    N = 2 ** 17
+    pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], N, K=c["K"])
+    st, y = gpu_yt(S, pr, H, "f32", c["seed"])
+    ref = orc(pr, Ho, c["seed"], np.arange(N))
+    r = rel(y, ref)
+    print(f"f32 C1@2^17: max rel {r.max():.3e} p99 {np.quantile(r, 0.99):.3e}")
+    assert r.max() <= TOL["f32"]
+    for k, f in enumerate(oracle.payoffs(ref, c["K"])):
+        e = oracle.estimate(f)
+        assert abs(st["mean"][k] - e["mean"]) <= 1e-6 * abs(e["mean"]), k
+
+
+def test_c1_full_size_sampled_paths(S, H, Ho):
+    """N = 2^22, M = 16, the benchmark's default plan; the oracle recomputes
+    the first and last 2^15 paths and a strided 2^16."""
+    c = W.CONFIGS["c1"]
+    pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
+    st, y = gpu_yt(S, pr, H, "f32", c["seed"])
+    sub = W.parity_subset(c["N"])
+    ref = orc(pr, Ho, c["seed"], sub)
+    r = rel(y[sub], ref)
+    print(f"f32 C1 full: max rel {r.max():.3e} over {len(sub)} paths")
+    assert r.max() <= TOL["f32"]
+    assert st["n"] == c["N"]
+    assert abs(st["mean"][0] - y.mean()) <= 1e-9 * abs(y.mean())
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f16", "f32"])
+def test_c2_full_size_sampled_paths(S, H, Ho, prec):
+    c = W.CONFIGS["c2"]
+    pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
+    st, y = gpu_yt(S, pr, H, prec, c["seed"])
+    N = c["N"]
+    sub = np.unique(np.concatenate([np.arange(4096), np.arange(N - 4096, N),
+                                    np.arange(0, N, N // 8192)]))
+    ref = orc(pr, Ho, c["seed"], sub)
+    r = rel(y[sub], ref)
+    print(f"{prec} C2 full: max rel {r.max():.3e} p99 {np.quantile(r, 0.99):.3e} over {len(sub)}")
+    assert r.max() <= TOL[prec]
+
+
+def test_results_independent_of_launch_plan(S, H):
+    c = W.CONFIGS["c1"]
+    pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 9, c["m"], 50_001, K=c["K"])
+    for prec in ("bf16", "f32"):
+        outs = []
+        for plan in (None, dict(waves_per_block=1, blocks_per_cu=1, grab=1),
+                     dict(waves_per_block=8, blocks_per_cu=1, grab=7),
+                     dict(waves_per_block=2, blocks_per_cu=3, grab=2)):
+            st, y = gpu_yt(S, pr, H, prec, 77, plan=plan)
+            outs.append((st, y))
+        for st, y in outs[1:]:
+            assert np.array_equal(y, outs[0][1])
+            assert st == outs[0][0]
+
+
+def test_path_offset_shards_compose(S, H):
+    c = W.CONFIGS["c1"]
+    full = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 6, c["m"], 3000, K=c["K"])
+    _, y = gpu_yt(S, full, H, "f32", 3)
+    part = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 6, c["m"], 1000, K=c["K"],
+                     path_offset=1500)
+    _, yp = gpu_yt(S, part, H, "f32", 3)
+    assert np.array_equal(yp, y[1500:2500])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16"])
+def test_eval_H_matches_oracle_forward(S, H, Ho, prec):
+    x = W.gbm_features(5000, seed=99)
+    ref = Ho.forward(x)
+    out = S.eval_H(H, torch.tensor(x, dtype=torch.float32, device="cuda"), prec=prec)
+    torch.cuda.synchronize()
+    got = out.double().cpu().numpy()
+    # inputs are rounded to FP32 before the call; compare against the oracle
+    # on the same rounded inputs
+    ref = Ho.forward(x.astype(np.float32).astype(np.float64))
+    tol = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-2, "f16": 5e-3}[prec]
+    assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 0.1)) <= tol
