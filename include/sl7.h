@@ -61,13 +61,19 @@ extern "C" {
 
 /* Arithmetic of the network GEMMs.  F64: everything in double.  F32: GEMMs
  * on FP32 MFMA.  BF16 / F16: hidden-layer and head GEMM operands rounded
- * (RNE) to bfloat16 / half on MFMA with FP32 accumulation; the first layer,
- * the interpolation and the state update stay FP32; the path mean is
- * reduced in FP64 in every mode. */
+ * (RNE) once to bfloat16 / half, one MFMA pass with FP32 accumulation.
+ * BF16X3 / F16X3: the same MFMA instructions on split operands
+ * x = hi + lo (hi = rn16(x), lo = rn16(x - hi)) for weights and
+ * activations, three passes hi*hi + hi*lo + lo*hi accumulated in FP32
+ * (close to FP32 accuracy; the one-pass forms carry a rounding bias per
+ * step).  In every mode the first layer, the interpolation and the state
+ * update stay FP32 and the path mean is reduced in FP64. */
 #define SL7_F64 0
 #define SL7_F32 1
 #define SL7_BF16 2
 #define SL7_F16 3
+#define SL7_BF16X3 4
+#define SL7_F16X3 5
 
 /* Hidden activations. */
 #define SL7_RELU 0
@@ -114,7 +120,7 @@ typedef struct {
 
 /* Launch plan of the fused kernel.  A plan changes speed, never results. */
 typedef struct {
-  int32_t waves_per_block; /* 1, 2, 4 or 8 wave64s per workgroup */
+  int32_t waves_per_block; /* 1, 2 or 4 wave64s per workgroup */
   int32_t blocks_per_cu;   /* persistent grid = blocks_per_cu x compute units */
   int32_t grab;            /* 64-path blocks taken per work-queue grab */
   int32_t reserved;
@@ -161,7 +167,7 @@ int sl7_eval_H(const sl7_mlp* H, int prec, const float* in_dev, int64_t B,
  * collocation map of the model (GBM: y_j = Y exp((mu - sigma^2/2) dt +
  * sigma sqrt(dt) x_j); OU: eq. 6.6 over one step); otherwise H (whose m
  * and d_in = 2 + n_theta must match).  prec: SL7_F64 for either map; F32
- * for either map; BF16 and F16 for the network only.
+ * for either map; BF16, F16, BF16X3 and F16X3 for the network only.
  * YT_dev: NULL, or device buffer of N values (double in F64 mode, float
  * otherwise) that receives Y_T per path.  stats_host: NULL or host struct;
  * when non-NULL the call synchronises `stream` before returning.

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libsl7.so")
 
 SL7_OK, SL7_EINVAL, SL7_EUNSUPPORTED, SL7_EHIP, SL7_ENOMEM, SL7_ENUMERIC, SL7_EIO = 0, -1, -2, -3, -4, -5, -6
 GBM, OU, CIR = 0, 1, 2
-F64, F32, BF16, F16 = 0, 1, 2, 3
+F64, F32, BF16, F16, BF16X3, F16X3 = 0, 1, 2, 3, 4, 5
 RELU, SOFTPLUS = 0, 1
 MAX_DIN = 8
 

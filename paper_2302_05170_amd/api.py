@@ -10,7 +10,8 @@ import torch
 
 from . import _lib as L
 
-PRECISIONS = {"f64": L.F64, "f32": L.F32, "bf16": L.BF16, "f16": L.F16}
+PRECISIONS = {"f64": L.F64, "f32": L.F32, "bf16": L.BF16, "f16": L.F16, "bf16x3": L.BF16X3,
+              "f16x3": L.F16X3}
 
 
 def _prec(p) -> int:

@@ -221,17 +221,38 @@ static uint16_t to_f16_bits(float f) {
   return u;
 }
 
+static float from_bf16_bits(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+static float from_f16_bits(uint16_t b) {
+  _Float16 h;
+  std::memcpy(&h, &b, 2);
+  return (float)h;
+}
+
 // Register layout of the MFMA kernels, one 16-byte slot per lane, slots in
 // the order the kernels load them.  Lane (g, n) = (lane / 16, lane % 16).
 static std::vector<uint32_t> pack_weights(const Mlp& H, int prec) {
-  const bool half = (prec == SL7_BF16 || prec == SL7_F16);
-  const int slots = half ? kSlotsH : kSlotsF;
+  const bool half = is_half(prec);
+  const bool x3 = is_x3(prec);
+  const bool bf = (prec == SL7_BF16 || prec == SL7_BF16X3);
+  const int slots = x3 ? kSlotsX3 : (half ? kSlotsH : kSlotsF);
   std::vector<uint32_t> out((size_t)slots * 64 * 4, 0u);
   auto put_f = [&](int s, int lane, int e, float v) {
     std::memcpy(&out[((size_t)s * 64 + lane) * 4 + e], &v, 4);
   };
+  // lo_part: store rn16(v - rn16(v)) instead of rn16(v)
+  bool lo_part = false;
   auto put_h = [&](int s, int lane, int i, float v) {
-    const uint16_t b = (prec == SL7_BF16) ? to_bf16_bits(v) : to_f16_bits(v);
+    uint16_t b = bf ? to_bf16_bits(v) : to_f16_bits(v);
+    if (lo_part) {
+      const float hi = bf ? from_bf16_bits(b) : from_f16_bits(b);
+      b = bf ? to_bf16_bits(v - hi) : to_f16_bits(v - hi);
+    }
     uint32_t& w = out[((size_t)s * 64 + lane) * 4 + i / 2];
     if (i % 2 == 0) w = (w & 0xffff0000u) | b; else w = (w & 0x0000ffffu) | ((uint32_t)b << 16);
   };
@@ -280,6 +301,22 @@ static std::vector<uint32_t> pack_weights(const Mlp& H, int prec) {
     for (int lane = 0; lane < 64; ++lane)
       for (int r = 0; r < 4; ++r)
         put_f(s, lane, r, (float)((double)H.W(0, 16 * b + 4 * (lane / 16) + r, 0) * H.d.in_scale[0]));
+  if (x3) {
+    lo_part = true;
+    auto feat = [](int c, int g, int i) { return 16 * (2 * c + i / 4) + 4 * g + (i % 4); };
+    for (int l = 0; l < 3; ++l)
+      for (int b = 0; b < 4; ++b)
+        for (int c = 0; c < 2; ++c, ++s)
+          for (int lane = 0; lane < 64; ++lane)
+            for (int i = 0; i < 8; ++i)
+              put_h(s, lane, i, H.W(l + 1, 16 * b + lane % 16, feat(c, lane / 16, i)));
+    for (int c = 0; c < 2; ++c, ++s)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int i = 0; i < 8; ++i) {
+          const int n = lane % 16;
+          put_h(s, lane, i, n < m ? H.W(4, n, feat(c, lane / 16, i)) : 0.f);
+        }
+  }
   return out;
 }
 
@@ -379,7 +416,7 @@ int check_problem(const sl7_problem* pr, const Mlp* H, int prec, const char* nam
     if (!(pr->theta[2] > 0.0)) return fail(SL7_EINVAL, "%s.theta[2] (gamma) must be > 0", name);
     if (!(pr->Y0 >= 0.0)) return fail(SL7_EINVAL, "%s.Y0 must be >= 0 for CIR", name);
   }
-  if (prec < SL7_F64 || prec > SL7_F16) return fail(SL7_EINVAL, "prec=%d unknown", prec);
+  if (prec < SL7_F64 || prec > SL7_F16X3) return fail(SL7_EINVAL, "prec=%d unknown", prec);
   if (!H) {
     if (pr->model == SL7_CIR) return fail(SL7_EUNSUPPORTED, "%s: CIR needs a network (no analytic map on the GPU)", name);
     if (prec != SL7_F64 && prec != SL7_F32)
@@ -470,16 +507,16 @@ int fill_nodes(int m, SimArgs& a, double* x_out) {
 
 int default_plan(int prec, sl7_plan* p) {
   p->waves_per_block = 4;
-  p->blocks_per_cu = (prec == SL7_BF16 || prec == SL7_F16) ? 2 : 1;
+  p->blocks_per_cu = (prec == SL7_BF16 || prec == SL7_F16) ? 2 : 1;  // register-limited occupancy
   p->grab = 1;
   p->reserved = 0;
   return SL7_OK;
 }
 
 int check_plan(const sl7_plan* p) {
-  if (p->waves_per_block != 1 && p->waves_per_block != 2 && p->waves_per_block != 4 &&
-      p->waves_per_block != 8 && p->waves_per_block != 16)
-    return fail(SL7_EINVAL, "plan.waves_per_block=%d not in {1,2,4,8,16}", p->waves_per_block);
+  // the fused kernels are compiled for at most 256 threads per workgroup
+  if (p->waves_per_block != 1 && p->waves_per_block != 2 && p->waves_per_block != 4)
+    return fail(SL7_EINVAL, "plan.waves_per_block=%d not in {1,2,4}", p->waves_per_block);
   if (p->blocks_per_cu < 1 || p->blocks_per_cu > 64) return fail(SL7_EINVAL, "plan.blocks_per_cu=%d outside [1, 64]", p->blocks_per_cu);
   if (p->grab < 1 || p->grab > 4096) return fail(SL7_EINVAL, "plan.grab=%d outside [1, 4096]", p->grab);
   return SL7_OK;
@@ -667,7 +704,7 @@ int sl7_mlp_set_params(sl7_mlp* H, const float* params) {
 int sl7_eval_H(const sl7_mlp* Hc, int prec, const float* in_dev, int64_t B, float* out_dev,
                void* stream) {
   if (!Hc) return fail(SL7_EINVAL, "H is NULL");
-  if (prec < SL7_F64 || prec > SL7_F16) return fail(SL7_EINVAL, "prec=%d unknown", prec);
+  if (prec < SL7_F64 || prec > SL7_F16X3) return fail(SL7_EINVAL, "prec=%d unknown", prec);
   if (B < 0) return fail(SL7_EINVAL, "B=%lld must be >= 0", (long long)B);
   if (B > 0 && (!in_dev || !out_dev)) return fail(SL7_EINVAL, "in_dev and out_dev must be non-NULL");
   Mlp* H = const_cast<Mlp*>(reinterpret_cast<const Mlp*>(Hc));
@@ -693,6 +730,10 @@ int sl7_simulate(const sl7_problem* pr, const sl7_mlp* Hc, int prec, uint64_t se
   Mlp* H = const_cast<Mlp*>(reinterpret_cast<const Mlp*>(Hc));
   int rc = check_problem(pr, H, prec, "pr");
   if (rc) return rc;
+  if (plan) {
+    rc = check_plan(plan);
+    if (rc) return rc;
+  }
   if (H) {
     rc = H->ensure_device(prec);
     if (rc) return rc;

@@ -224,7 +224,7 @@ extern "C" int sl7_autotune(const sl7_problem* shape, const sl7_mlp* Hc, int pre
   std::lock_guard<std::mutex> lk(ws.mu);
   hipStream_t s = (hipStream_t)stream;
   std::vector<sl7_plan> cands;
-  const int wpb[] = {1, 2, 4, 8};
+  const int wpb[] = {1, 2, 4};
   const int bpc[] = {1, 2, 3, 4, 8};
   const int grabs[] = {1, 4};
   for (int w : wpb)

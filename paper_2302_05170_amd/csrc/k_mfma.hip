@@ -114,6 +114,120 @@ __device__ __forceinline__ f32x4 chain_h(const NetRegsH<P>& R, typename H16<P>::
 }
 
 // ------------------------------------------------------------------------
+// Three-pass split operands: x = hi + lo with hi = rn(x) and lo = rn(x - hi)
+// in the 16-bit type, for weights and activations; each product is
+// hi*hi + hi*lo + lo*hi accumulated in FP32 (the lo*lo term, ~2^-16 of the
+// product for BF16, is dropped).  Removes the rounding bias of one-pass
+// 16-bit operands at three times the MFMA work.
+// ------------------------------------------------------------------------
+template <int P>
+struct Split16;
+
+template <>
+struct Split16<SL7_BF16X3> {
+  typedef bf16x8 v8;
+  typedef bf16x2 v2;
+  static constexpr int base = SL7_BF16;
+};
+
+template <>
+struct Split16<SL7_F16X3> {
+  typedef f16x8 v8;
+  typedef f16x2 v2;
+  static constexpr int base = SL7_F16;
+};
+
+// ReLU in FP32, then the (hi, lo) pair of B operands for eight activations.
+template <int P>
+__device__ __forceinline__ void split8(f32x4 a, f32x4 b, typename Split16<P>::v8& hi,
+                                       typename Split16<P>::v8& lo) {
+  typedef typename Split16<P>::v2 v2;
+  const float v[8] = {fmaxf(a[0], 0.f), fmaxf(a[1], 0.f), fmaxf(a[2], 0.f), fmaxf(a[3], 0.f),
+                      fmaxf(b[0], 0.f), fmaxf(b[1], 0.f), fmaxf(b[2], 0.f), fmaxf(b[3], 0.f)};
+  u32x4 wh, wl;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const v2 h = __builtin_convertvector((f32x2){v[2 * q], v[2 * q + 1]}, v2);
+    const f32x2 back = __builtin_convertvector(h, f32x2);
+    const v2 l = __builtin_convertvector((f32x2){v[2 * q] - back[0], v[2 * q + 1] - back[1]}, v2);
+    wh[q] = __builtin_bit_cast(uint32_t, h);
+    wl[q] = __builtin_bit_cast(uint32_t, l);
+  }
+  hi = __builtin_bit_cast(typename Split16<P>::v8, wh);
+  lo = __builtin_bit_cast(typename Split16<P>::v8, wl);
+}
+
+template <int P>
+struct NetRegsX3 {
+  typedef typename Split16<P>::v8 v8;
+  v8 A[3][4][2], Al[3][4][2];
+  v8 Ah[2], Ahl[2];
+  f32x4 C[3][4];
+  f32x4 Ch;
+  f32x4 wY[4];
+
+  __device__ __forceinline__ void load(const u32x4* __restrict__ wp, int lane) {
+    int s = 0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) A[l][b][c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) Ah[c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) C[l][b] = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
+    Ch = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) wY[b] = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) Al[l][b][c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) Ahl[c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
+  }
+};
+
+template <int P>
+__device__ __forceinline__ f32x4 chain_x3(const NetRegsX3<P>& R, const f32x4 z[4]) {
+  typedef typename Split16<P>::v8 v8;
+  constexpr int B = Split16<P>::base;
+  v8 h0, h1, l0, l1;
+  split8<P>(z[0], z[1], h0, l0);
+  split8<P>(z[2], z[3], h1, l1);
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    f32x4 acc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.Al[l][b][0], h0, R.C[l][b]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.Al[l][b][1], h1, acc[b]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.A[l][b][0], l0, acc[b]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.A[l][b][1], l1, acc[b]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.A[l][b][0], h0, acc[b]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.A[l][b][1], h1, acc[b]);
+    split8<P>(acc[0], acc[1], h0, l0);
+    split8<P>(acc[2], acc[3], h1, l1);
+  }
+  f32x4 y = H16<B>::mfma(R.Ahl[0], h0, R.Ch);
+  y = H16<B>::mfma(R.Ahl[1], h1, y);
+  y = H16<B>::mfma(R.Ah[0], l0, y);
+  y = H16<B>::mfma(R.Ah[1], l1, y);
+  y = H16<B>::mfma(R.Ah[0], h0, y);
+  return H16<B>::mfma(R.Ah[1], h1, y);
+}
+
+// ------------------------------------------------------------------------
 // FP32 operands (v_mfma_f32_16x16x4_f32): K block kb = 4 b_in + r takes
 // register r of block b_in of the previous layer's accumulator.
 // ------------------------------------------------------------------------
@@ -320,6 +434,20 @@ struct NetF {
   }
 };
 
+template <int P>
+struct NetX3 {
+  NetRegsX3<P> R;
+  __device__ __forceinline__ f32x4 eval(float Y, const f32x4 c0[4]) const {
+    f32x4 z[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) z[b][r] = fmaf(Y, R.wY[b][r], c0[b][r]);
+    return chain_x3<P>(R, z);
+  }
+  __device__ __forceinline__ f32x4 eval_z0(const f32x4 z[4]) const { return chain_x3<P>(R, z); }
+};
+
 template <class Net>
 __device__ __forceinline__ void sim_persistent(const SimArgs& a, const Net& net) {
   const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
@@ -345,6 +473,13 @@ void k_sim_mfma_h(SimArgs a) {
   sim_persistent(a, net);
 }
 
+template <int P>
+__global__ __launch_bounds__(256) void k_sim_mfma_x3(SimArgs a) {
+  NetX3<P> net;
+  net.R.load((const u32x4*)a.wpack, threadIdx.x & 63);
+  sim_persistent(a, net);
+}
+
 __global__ __launch_bounds__(256) void k_sim_mfma_f(SimArgs a) {
   NetF net;
   net.R.load((const u32x4*)a.wpack, threadIdx.x & 63);
@@ -356,6 +491,8 @@ hipError_t launch_sim_mfma(int prec, const SimArgs& a, int grid, int waves_per_b
   dim3 g(grid), b(64 * waves_per_block);
   if (prec == SL7_BF16) hipLaunchKernelGGL(k_sim_mfma_h<SL7_BF16>, g, b, 0, s, a);
   else if (prec == SL7_F16) hipLaunchKernelGGL(k_sim_mfma_h<SL7_F16>, g, b, 0, s, a);
+  else if (prec == SL7_BF16X3) hipLaunchKernelGGL(k_sim_mfma_x3<SL7_BF16X3>, g, b, 0, s, a);
+  else if (prec == SL7_F16X3) hipLaunchKernelGGL(k_sim_mfma_x3<SL7_F16X3>, g, b, 0, s, a);
   else hipLaunchKernelGGL(k_sim_mfma_f, g, b, 0, s, a);
   return hipGetLastError();
 }
@@ -424,6 +561,15 @@ __global__ __launch_bounds__(256) void k_eval_mfma_h(const void* wpack, const fl
   eval_rows(net, w0n, c0n, d_in, m, in, B, out);
 }
 
+template <int P>
+__global__ __launch_bounds__(256) void k_eval_mfma_x3(const void* wpack, const float* w0n,
+                                                      const float* c0n, int d_in, int m,
+                                                      const float* in, int64_t B, float* out) {
+  NetX3<P> net;
+  net.R.load((const u32x4*)wpack, threadIdx.x & 63);
+  eval_rows(net, w0n, c0n, d_in, m, in, B, out);
+}
+
 __global__ __launch_bounds__(256) void k_eval_mfma_f(const void* wpack, const float* w0n,
                                                      const float* c0n, int d_in, int m,
                                                      const float* in, int64_t B, float* out) {
@@ -442,6 +588,10 @@ hipError_t launch_eval_mfma(int prec, const void* wpack, const float* w0n, const
     hipLaunchKernelGGL(k_eval_mfma_h<SL7_BF16>, dim3(grid), dim3(256), 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
   else if (prec == SL7_F16)
     hipLaunchKernelGGL(k_eval_mfma_h<SL7_F16>, dim3(grid), dim3(256), 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
+  else if (prec == SL7_BF16X3)
+    hipLaunchKernelGGL(k_eval_mfma_x3<SL7_BF16X3>, dim3(grid), dim3(256), 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
+  else if (prec == SL7_F16X3)
+    hipLaunchKernelGGL(k_eval_mfma_x3<SL7_F16X3>, dim3(grid), dim3(256), 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
   else
     hipLaunchKernelGGL(k_eval_mfma_f, dim3(grid), dim3(256), 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
   return hipGetLastError();

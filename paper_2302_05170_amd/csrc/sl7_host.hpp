@@ -53,7 +53,7 @@ struct Mlp {
   std::string meta;
   std::mutex mu;
   int device = -1;
-  std::unique_ptr<DevBuf> pack[4];  // MFMA register layouts, by precision
+  std::unique_ptr<DevBuf> pack[6];  // MFMA register layouts, by precision
   std::unique_ptr<DevBuf> net64, w0full, w0n, c0n;
 
   void layout();

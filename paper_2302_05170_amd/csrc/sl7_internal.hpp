@@ -62,6 +62,11 @@ struct SimArgs {
 //             + C hidden (12) + C head (1) + wY (4)
 constexpr int kSlotsH = 24 + 2 + 12 + 1 + 4;  // 43
 constexpr int kSlotsF = 48 + 4 + 12 + 1 + 4;  // 69
+//   BF16X3/F16X3: the BF16/F16 slots, then the lo parts of A hidden (24) and A head (2)
+constexpr int kSlotsX3 = kSlotsH + 24 + 2;    // 69
+
+inline bool is_x3(int prec) { return prec == SL7_BF16X3 || prec == SL7_F16X3; }
+inline bool is_half(int prec) { return prec == SL7_BF16 || prec == SL7_F16 || is_x3(prec); }
 
 // FP64 network layout for the per-lane kernel: wY[64] (first-layer weight of
 // Y times its input scale), then hidden layers 1..3 (W 64x64 row-major, b),

@@ -138,3 +138,18 @@ def test_simulate_rejects_mismatched_network_and_precision(L):
     assert rc == L.SL7_EUNSUPPORTED
     rc, msg = _sim_rc(L, prec=9)
     assert rc == L.SL7_EINVAL
+
+
+def test_plans_beyond_the_kernels_launch_bounds_are_rejected(L):
+    import paper_2302_05170_amd as S
+    H = S.Mlp.load(WEIGHTS)
+    pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 4, 5, 100).c()
+    for bad in (dict(waves_per_block=8), dict(waves_per_block=3), dict(blocks_per_cu=0),
+                dict(grab=0)):
+        plan = L.Plan()
+        plan.waves_per_block, plan.blocks_per_cu, plan.grab = 4, 1, 1
+        for k, v in bad.items():
+            setattr(plan, k, v)
+        rc = L.lib().sl7_simulate(ctypes.byref(pr), H.handle, L.BF16, 1, None, None,
+                                  ctypes.byref(plan), None)
+        assert rc == L.SL7_EINVAL, bad
