@@ -186,6 +186,33 @@ int sl7_simulate_batched(const sl7_problem* prs, int n, const sl7_mlp* H,
                          int prec, uint64_t seed, sl7_stats* stats_host,
                          const sl7_plan* plan, int use_graph, void* stream);
 
+/* --- reverse-mode sensitivities ---------------------------------------- */
+/* Pathwise sensitivities of E[f(Y_T)] (f = Y_T for payoff 0, max(Y_T-K, 0)
+ * for payoff 1) to Y0 and theta, by a reverse (adjoint) sweep through all M
+ * steps of every path: the forward pass stores Y every ckpt_every steps,
+ * the reverse pass recomputes the states in between from the same Philox
+ * counters.  grad[0] = dE/dY0, grad[1 + k] = dE/dtheta_k; *_se are the
+ * Monte Carlo standard errors of the pathwise estimators.  f'(K) = 0 for
+ * the call; ReLU'(0) = 0; a clamped CIR step passes no gradient. */
+typedef struct {
+  double value, value_se;
+  double grad[5], grad_se[5];
+  int32_t n_grad, reserved;
+} sl7_greeks;
+
+/* Workspace size (bytes) for sl7_adjoint: checkpoints
+ * ceil(M / ckpt_every) x N states plus block sums. 0 for bad arguments. */
+size_t sl7_adjoint_ws_bytes(const sl7_problem* pr, int prec, int ckpt_every);
+
+/* H == NULL: analytic map (GBM, OU).  prec: SL7_F64 or SL7_F32 (the
+ * accumulation of the theta-gradients is FP64 in both).  ws_dev: caller's
+ * device workspace of at least sl7_adjoint_ws_bytes.  per_path_dev: NULL or
+ * device [N x (2 + n_theta)] doubles receiving (f, df/dY0, df/dtheta...)
+ * per path.  ckpt_every in [1, 32].  Synchronises `stream`. */
+int sl7_adjoint(const sl7_problem* pr, const sl7_mlp* H, int prec, uint64_t seed,
+                int payoff, int ckpt_every, sl7_greeks* out_host, double* per_path_dev,
+                void* ws_dev, size_t ws_bytes, void* stream);
+
 /* --- offline stage (Algorithm I, step 1) ------------------------------- */
 /* Training labels: for each of the n rows of feats_dev ([n x d_in] FP32,
  * device; row = (Y, dt, theta...), d_in = 2 + n_theta(model)), n_paths

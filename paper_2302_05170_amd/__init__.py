@@ -5,5 +5,5 @@ C ABI in include/sl7.h).  This package only marshals arguments: torch
 tensors serve as device buffers and streams.
 """
 from ._lib import (BF16, CIR, F16, F32, F64, GBM, OU, RELU, SOFTPLUS, Sl7Error)  # noqa: F401
-from .api import (Mlp, PRECISIONS, Problem, eval_H, gh_nodes, labels, simulate,  # noqa: F401
-                  simulate_batched, train, train_grad)
+from .api import (Mlp, PRECISIONS, Problem, SL7Adjoint, adjoint, eval_H, gh_nodes,  # noqa: F401
+                  labels, simulate, simulate_batched, train, train_grad)

@@ -62,7 +62,15 @@ SIGNATURES = {
                                   c_u64, c_i64, c_p, c_p]),
     "sl7_train": (ctypes.c_int, [c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_p]),
     "sl7_train_grad": (ctypes.c_int, [c_p, c_p, c_p, c_i64, c_p, c_p, c_p]),
+    "sl7_adjoint_ws_bytes": (ctypes.c_size_t, [c_p, ctypes.c_int, ctypes.c_int]),
+    "sl7_adjoint": (ctypes.c_int, [c_p, c_p, ctypes.c_int, c_u64, ctypes.c_int, ctypes.c_int, c_p,
+                                   c_p, c_p, ctypes.c_size_t, c_p]),
 }
+
+
+class Greeks(ctypes.Structure):
+    _fields_ = [("value", c_dbl), ("value_se", c_dbl), ("grad", c_dbl * 5), ("grad_se", c_dbl * 5),
+                ("n_grad", c_i32), ("reserved", c_i32)]
 
 
 class TrainSpec(ctypes.Structure):

@@ -230,3 +230,50 @@ def train_grad(H: Mlp, X: torch.Tensor, Y: torch.Tensor, stream=None):
     L.check(L.lib().sl7_train_grad(H.handle, _ptr(X), _ptr(Y), X.shape[0], _ptr(g),
                                    ctypes.byref(loss), _stream(stream)))
     return loss.value, g
+
+
+def adjoint(pr: Problem, H: Mlp | None = None, prec="f64", seed: int = 42, payoff: int = 1,
+            ckpt_every: int = 4, per_path: bool = False, stream=None):
+    """Pathwise Greeks by the reverse sweep (sl7_adjoint).  Returns a dict
+    with value, value_se, grad [dE/dY0, dE/dtheta...], grad_se and, when
+    per_path, a [N, 2 + n_theta] float64 tensor of (f, df/dY0, df/dtheta)."""
+    p = _prec(prec)
+    cp = pr.c()
+    nbytes = L.lib().sl7_adjoint_ws_bytes(ctypes.byref(cp), p, int(ckpt_every))
+    if nbytes == 0:
+        L.check(L.SL7_EINVAL)
+    ws = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+    nth = 2 if pr.model == L.GBM else 3
+    pp = torch.empty((int(pr.N), 2 + nth), dtype=torch.float64, device="cuda") if per_path else None
+    g = L.Greeks()
+    L.check(L.lib().sl7_adjoint(ctypes.byref(cp), H.handle if H is not None else None, p,
+                                int(seed), int(payoff), int(ckpt_every), ctypes.byref(g), _ptr(pp),
+                                _ptr(ws), int(nbytes), _stream(stream)))
+    out = {"value": g.value, "value_se": g.value_se,
+           "grad": [g.grad[k] for k in range(g.n_grad)],
+           "grad_se": [g.grad_se[k] for k in range(g.n_grad)]}
+    return (out, pp) if per_path else out
+
+
+class SL7Adjoint(torch.autograd.Function):
+    """E[f(Y_T)] as a differentiable function of (Y0, theta): forward runs the
+    adjoint sweep once (value and pathwise Greeks); backward scales the stored
+    Greeks by the incoming gradient.
+
+        value = SL7Adjoint.apply(Y0, theta, problem, H, prec, seed, payoff, ckpt)
+    """
+
+    @staticmethod
+    def forward(ctx, Y0, theta, problem: Problem, H, prec="f64", seed=42, payoff=1, ckpt=4):
+        pr = Problem(problem.model, tuple(float(v) for v in theta.detach().cpu().tolist()),
+                     float(Y0.detach().cpu()), problem.T, problem.M, problem.m, problem.N,
+                     problem.K, problem.path_offset, problem.instance)
+        g = adjoint(pr, H, prec=prec, seed=seed, payoff=payoff, ckpt_every=ckpt)
+        ctx.save_for_backward(torch.tensor(g["grad"], dtype=torch.float64))
+        return torch.tensor(g["value"], dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, gout):
+        (grad,) = ctx.saved_tensors
+        gout = gout.to(torch.float64).cpu()
+        return gout * grad[0], gout * grad[1:], None, None, None, None, None, None

@@ -1,0 +1,184 @@
+// Host side of the adjoint sweep (pathwise Greeks of the 7L online stage).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <vector>
+
+#include "sl7_adjoint.hpp"
+#include "sl7_host.hpp"
+
+using namespace sl7;
+
+namespace {
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+struct WsLayout {
+  size_t ckpt, parts, result, total;
+};
+
+WsLayout layout_of(const sl7_problem* pr, int prec, int ckpt) {
+  const size_t el = prec == SL7_F64 ? sizeof(double) : sizeof(float);
+  const int64_t nseg = (pr->M + ckpt - 1) / ckpt;
+  const int64_t nb = (pr->N + 63) / 64;
+  WsLayout L;
+  L.ckpt = 0;
+  L.parts = align256(el * (size_t)nseg * (size_t)pr->N);
+  L.result = L.parts + align256(sizeof(AdjPartial) * (size_t)nb);
+  L.total = L.result + align256(sizeof(double) * 12);
+  return L;
+}
+
+// d(A_j, B_j)/dtheta_k of the affine analytic maps y_j = A_j Y + B_j.
+void analytic_derivs(const sl7_problem& pr, const double* x, AdjArgs& a) {
+  const double dt = pr.T / pr.M;
+  for (int k = 0; k < 4; ++k)
+    for (int j = 0; j < kMaxM; ++j) a.dA[k][j] = a.dB[k][j] = 0.0;
+  if (pr.model == SL7_GBM) {
+    const double sig = pr.theta[0], mu = pr.theta[1];
+    for (int j = 0; j < pr.m; ++j) {
+      const double A = std::exp((mu - 0.5 * sig * sig) * dt + sig * std::sqrt(dt) * x[j]);
+      a.dA[0][j] = A * (-sig * dt + std::sqrt(dt) * x[j]);
+      a.dA[1][j] = A * dt;
+    }
+  } else if (pr.model == SL7_OU) {
+    const double ybar = pr.theta[0], sig = pr.theta[1], lam = pr.theta[2];
+    const double e = std::exp(-lam * dt);
+    const double v = (1.0 - e * e) / (2.0 * lam);
+    const double dv = (4.0 * lam * dt * e * e - 2.0 * (1.0 - e * e)) / (4.0 * lam * lam);
+    for (int j = 0; j < pr.m; ++j) {
+      a.dA[2][j] = -dt * e;
+      a.dB[0][j] = 1.0 - e;
+      a.dB[1][j] = std::sqrt(v) * x[j];
+      a.dB[2][j] = ybar * dt * e + sig * 0.5 / std::sqrt(v) * dv * x[j];
+    }
+  }
+}
+
+}  // namespace
+
+namespace sl7 {
+
+// Lane layout of the network in T plus the first-layer weights of theta
+// (times their input scales), for the adjoint kernels.
+int Mlp::ensure_adjoint(int prec) {
+  int rc = ensure_device(SL7_F64);  // FP64 lane layout
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(mu);
+  const int nth = d.d_in - 2;
+  std::vector<double> wt((size_t)nth * 64);
+  for (int k = 0; k < nth; ++k)
+    for (int o = 0; o < 64; ++o) wt[k * 64 + o] = (double)W(0, o, 2 + k) * d.in_scale[2 + k];
+  if (prec == SL7_F64) {
+    if (wth64) return SL7_OK;
+    wth64.reset(new DevBuf());
+    rc = wth64->reserve(wt.size() * sizeof(double));
+    if (rc) return rc;
+    const hipError_t e = hipMemcpy(wth64->p, wt.data(), wt.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "upload theta weights");
+    return SL7_OK;
+  }
+  if (net32 && wth32) return SL7_OK;
+  std::vector<float> v;
+  for (int o = 0; o < 64; ++o) v.push_back((float)((double)W(0, o, 0) * d.in_scale[0]));
+  for (int l = 1; l <= 3; ++l) {
+    for (int o = 0; o < 64; ++o)
+      for (int k = 0; k < 64; ++k) v.push_back(W(l, o, k));
+    for (int o = 0; o < 64; ++o) v.push_back(b(l, o));
+  }
+  for (int j = 0; j < d.m; ++j)
+    for (int k = 0; k < 64; ++k) v.push_back(W(4, j, k));
+  for (int j = 0; j < d.m; ++j) v.push_back(b(4, j));
+  std::vector<float> wt32(wt.begin(), wt.end());
+  net32.reset(new DevBuf());
+  wth32.reset(new DevBuf());
+  rc = net32->reserve(v.size() * sizeof(float));
+  if (!rc) rc = wth32->reserve(wt32.size() * sizeof(float));
+  if (rc) return rc;
+  hipError_t e = hipMemcpy(net32->p, v.data(), v.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(wth32->p, wt32.data(), wt32.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "upload FP32 lane weights");
+  return SL7_OK;
+}
+
+}  // namespace sl7
+
+extern "C" size_t sl7_adjoint_ws_bytes(const sl7_problem* pr, int prec, int ckpt_every) {
+  if (!pr || pr->N < 1 || pr->M < 1 || ckpt_every < 1) return 0;
+  return layout_of(pr, prec, ckpt_every).total;
+}
+
+extern "C" int sl7_adjoint(const sl7_problem* pr, const sl7_mlp* Hc, int prec, uint64_t seed,
+                           int payoff, int ckpt_every, sl7_greeks* out, double* per_path_dev,
+                           void* ws_dev, size_t ws_bytes, void* stream) {
+  Mlp* H = const_cast<Mlp*>(reinterpret_cast<const Mlp*>(Hc));
+  int rc = check_problem(pr, H, prec, "pr");
+  if (rc) return rc;
+  if (prec != SL7_F64 && prec != SL7_F32) return fail(SL7_EUNSUPPORTED, "the adjoint runs in F64 or F32");
+  if (payoff != 0 && payoff != 1) return fail(SL7_EINVAL, "payoff=%d must be 0 (Y_T) or 1 (call)", payoff);
+  if (ckpt_every < 1 || ckpt_every > 32) return fail(SL7_EINVAL, "ckpt_every=%d outside [1, 32]", ckpt_every);
+  if (!out) return fail(SL7_EINVAL, "out is NULL");
+  if (!ws_dev) return fail(SL7_EINVAL, "ws_dev is NULL");
+  const WsLayout Lw = layout_of(pr, prec, ckpt_every);
+  if (ws_bytes < Lw.total) return fail(SL7_EINVAL, "ws_bytes=%zu < %zu needed", ws_bytes, Lw.total);
+  if (H) {
+    rc = H->ensure_adjoint(prec);
+    if (rc) return rc;
+  }
+  int dev;
+  rc = current_device(&dev);
+  if (rc) return rc;
+  Workspace& ws = workspace(dev);
+  std::lock_guard<std::mutex> lk(ws.mu);
+  hipStream_t s = (hipStream_t)stream;
+  SimArgs sa;
+  rc = prepare_instances(pr, 1, H, prec, seed, nullptr, s, ws, sa);
+  if (rc) return rc;
+  AdjArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.inst = sa.inst;
+  a.inst_N = pr->N;
+  a.m = pr->m;
+  a.n_theta = n_theta(pr->model);
+  a.ckpt = ckpt_every;
+  a.payoff = payoff;
+  for (int j = 0; j < kMaxM; ++j) {
+    a.xs[j] = sa.xs[j];
+    a.ls[j] = sa.ls[j];
+    a.xd[j] = sa.xd[j];
+    a.ld[j] = sa.ld[j];
+  }
+  analytic_derivs(*pr, sa.xd, a);
+  const char* instp = (const char*)ws.inst.p;
+  if (H) {
+    a.net = prec == SL7_F64 ? H->net64->p : H->net32->p;
+    a.wtheta = prec == SL7_F64 ? H->wth64->p : H->wth32->p;
+    a.c0 = instp + (prec == SL7_F64 ? offsetof(InstDev, c0d) : offsetof(InstDev, c0));
+  }
+  char* w = (char*)ws_dev;
+  a.ckpt_buf = w + Lw.ckpt;
+  a.partials = (AdjPartial*)(w + Lw.parts);
+  a.result = (double*)(w + Lw.result);
+  a.per_path = per_path_dev;
+  a.seed = seed;
+  const int64_t nb = (pr->N + 63) / 64;
+  hipError_t e = launch_adjoint(prec, H ? 1 : 0, a, nb, s);
+  if (e != hipSuccess) return hip_fail(e, "launch adjoint");
+  double res[12];
+  e = hipMemcpyAsync(res, a.result, sizeof(res), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint result");
+  std::memset(out, 0, sizeof(*out));
+  out->value = res[0];
+  out->value_se = res[6];
+  out->n_grad = 1 + a.n_theta;
+  for (int q = 0; q < out->n_grad; ++q) {
+    out->grad[q] = res[1 + q];
+    out->grad_se[q] = res[7 + q];
+  }
+  for (int q = 0; q < out->n_grad; ++q)
+    if (!std::isfinite(out->grad[q])) return fail(SL7_ENUMERIC, "non-finite sensitivity %d", q);
+  return SL7_OK;
+}

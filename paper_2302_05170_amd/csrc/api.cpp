@@ -200,6 +200,9 @@ float Mlp::b(int l, int o) const { return params[b_off[l] + o]; }
 void Mlp::drop_device() {
   for (auto& p : pack) p.reset();
   net64.reset();
+  net32.reset();
+  wth64.reset();
+  wth32.reset();
   w0full.reset();
   w0n.reset();
   c0n.reset();

@@ -1,0 +1,307 @@
+// Reverse-mode (adjoint) sweep of the Seven-League online stage: pathwise
+// sensitivities of E[f(Y_T)] to Y0 and theta.
+//
+// Forward: the 7L loop (Algorithm I, steps 3-6) storing Y every `ckpt`
+// steps.  Reverse, segment by segment from the last: recompute the segment's
+// states from its checkpoint with the same Philox counters (no random state
+// is stored), then for each step backwards
+//   ybar_j = lambda * L_j(X)                 (L_j the Lagrange basis at X)
+//   lambda <- sum_j ybar_j dy_j/dY,  thetabar += sum_j ybar_j dy_j/dtheta
+// where dy/d(Y, theta) comes from the analytic map or from back-propagation
+// through the network (eq. 6.3/6.4; ReLU masks kept in registers).  Starts
+// from lambda = f'(Y_T); a CIR step clamped to 0 passes no gradient.
+// thetabar accumulates in FP64.  One path per lane, one 64-path block per
+// workgroup; block sums in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "sl7_adjoint.hpp"
+
+namespace sl7 {
+
+template <typename T>
+__device__ __forceinline__ T step_normal(const AdjArgs& a, int i, int64_t gp, uint32_t tag) {
+  const u32x4 r = philox_step_quad(a.seed, (uint32_t)(i >> 2), gp, tag);
+  T x[4];
+  if constexpr (sizeof(T) == 8) normals4_f64(r, x); else normals4_f32(r, x);
+  const int u = i & 3;
+  return u == 0 ? x[0] : (u == 1 ? x[1] : (u == 2 ? x[2] : x[3]));
+}
+
+// Collocation points at Y; for the network the ReLU masks of the four hidden
+// layers are returned in mask[l*2 + (unit/32)] bit (unit%32).
+template <typename T, bool NET>
+__device__ __forceinline__ void colloc(const AdjArgs& a, const InstDev& I, T Y, T* hA, T* hB,
+                                       T y[kMaxM], uint32_t mask[8]) {
+  const int m = a.m;
+  if constexpr (NET) {
+    const T* W = (const T*)a.net;
+    const T* c0 = (const T*)a.c0;
+    for (int q = 0; q < 8; ++q) mask[q] = 0u;
+    for (int o = 0; o < 64; ++o) {
+      const T z = fma(W[o], Y, c0[o]);
+      if (z > T(0)) mask[o >> 5] |= 1u << (o & 31);
+      hA[o * 64] = z > T(0) ? z : T(0);
+    }
+    const T* Wl = W + 64;
+    T* hin = hA;
+    T* hout = hB;
+    for (int l = 1; l < 4; ++l) {
+      const T* bl = Wl + 64 * 64;
+      for (int o = 0; o < 64; ++o) {
+        T s = bl[o];
+        const T* row = Wl + o * 64;
+#pragma unroll 8
+        for (int k = 0; k < 64; ++k) s = fma(row[k], hin[k * 64], s);
+        if (s > T(0)) mask[2 * l + (o >> 5)] |= 1u << (o & 31);
+        hout[o * 64] = s > T(0) ? s : T(0);
+      }
+      Wl += 64 * 64 + 64;
+      T* t = hin; hin = hout; hout = t;
+    }
+    const T* bh = Wl + 64 * m;
+#pragma unroll
+    for (int j = 0; j < kMaxM; ++j) {
+      if (j < m) {
+        T s = bh[j];
+        const T* row = Wl + j * 64;
+        for (int k = 0; k < 64; ++k) s = fma(row[k], hin[k * 64], s);
+        y[j] = s;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kMaxM; ++j) y[j] = (T)I.A[j] * Y + (T)I.B[j];
+  }
+}
+
+// Lagrange basis at X (second barycentric form; a node hit gives a unit
+// vector) and the interpolated value.
+template <typename T>
+__device__ __forceinline__ T basis(const AdjArgs& a, T X, const T y[kMaxM], T L[kMaxM]) {
+  const int m = a.m;
+  int hit = -1;
+  T den = T(0);
+#pragma unroll
+  for (int j = 0; j < kMaxM; ++j) {
+    L[j] = T(0);
+    if (j < m) {
+      const T xj = sizeof(T) == 8 ? (T)a.xd[j] : (T)a.xs[j];
+      const T lj = sizeof(T) == 8 ? (T)a.ld[j] : (T)a.ls[j];
+      if (X == xj) hit = j;
+      L[j] = lj / (X - xj);
+      den += L[j];
+    }
+  }
+  T g = T(0);
+#pragma unroll
+  for (int j = 0; j < kMaxM; ++j) {
+    if (j < m) {
+      L[j] = hit >= 0 ? (j == hit ? T(1) : T(0)) : L[j] / den;
+      g += L[j] * y[j];
+    }
+  }
+  return g;
+}
+
+// Vector-Jacobian product of the collocation map: given ybar, returns
+// dY = ybar . dy/dY and adds ybar . dy/dtheta_k into thb[k].
+template <typename T, bool NET>
+__device__ __forceinline__ T vjp(const AdjArgs& a, const InstDev& I, T Y, const T ybar[kMaxM],
+                                 const uint32_t mask[8], T* dA, T* dB, double thb[4]) {
+  const int m = a.m;
+  const int nth = a.n_theta;
+  if constexpr (NET) {
+    const T* W = (const T*)a.net;
+    const T* Wh = W + 64 + 3 * (64 * 64 + 64);
+    // cotangent of the last hidden layer
+    for (int k = 0; k < 64; ++k) {
+      T g = T(0);
+#pragma unroll
+      for (int j = 0; j < kMaxM; ++j)
+        if (j < m) g = fma(Wh[j * 64 + k], ybar[j], g);
+      dA[k * 64] = ((mask[6 + (k >> 5)] >> (k & 31)) & 1u) ? g : T(0);
+    }
+    T* dn = dA;
+    T* dp = dB;
+    for (int l = 3; l >= 1; --l) {
+      const T* Wl = W + 64 + (l - 1) * (64 * 64 + 64);
+      for (int k = 0; k < 64; ++k) {
+        T g = T(0);
+#pragma unroll 8
+        for (int o = 0; o < 64; ++o) g = fma(Wl[o * 64 + k], dn[o * 64], g);
+        dp[k * 64] = ((mask[2 * (l - 1) + (k >> 5)] >> (k & 31)) & 1u) ? g : T(0);
+      }
+      T* t = dn; dn = dp; dp = t;
+    }
+    // dn: cotangent of the first hidden layer's pre-activation
+    const T* wT = (const T*)a.wtheta;
+    T dY = T(0);
+    double acc[4] = {0, 0, 0, 0};
+    for (int o = 0; o < 64; ++o) {
+      const T d = dn[o * 64];
+      dY = fma(W[o], d, dY);
+      for (int k = 0; k < nth; ++k) acc[k] += (double)(wT[k * 64 + o] * d);
+    }
+    for (int k = 0; k < nth; ++k) thb[k] += acc[k];
+    return dY;
+  } else {
+    T dY = T(0);
+#pragma unroll
+    for (int j = 0; j < kMaxM; ++j)
+      if (j < m) dY = fma(ybar[j], (T)I.A[j], dY);
+    for (int k = 0; k < nth; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < kMaxM; ++j)
+        if (j < m) s += (double)ybar[j] * ((double)Y * a.dA[k][j] + a.dB[k][j]);
+      thb[k] += s;
+    }
+    return dY;
+  }
+}
+
+template <typename T, bool NET>
+__global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
+  extern __shared__ double lds_adj[];
+  const InstDev& I = a.inst[0];
+  const int lane = threadIdx.x;
+  T* hA = (T*)lds_adj + lane;
+  T* hB = hA + 64 * 64;
+  T* ybuf = hB + 64 * 64;  // [ckpt][64]
+  const int64_t p = (int64_t)blockIdx.x * 64 + lane;
+  const bool valid = p < I.N;
+  const int64_t gp = I.path_offset + p;
+  const uint32_t tag = (uint32_t)I.tag;
+  const int M = I.M, k = a.ckpt;
+  const bool clamp = I.clamp_zero != 0;
+  T* ck = (T*)a.ckpt_buf;
+  T y[kMaxM], L[kMaxM], ybar[kMaxM];
+  uint32_t mask[8];
+  // forward with checkpoints
+  T Y = sizeof(T) == 8 ? (T)I.Y0 : (T)I.Y0_f;
+  for (int i = 0; i < M; ++i) {
+    if (i % k == 0 && valid) ck[(int64_t)(i / k) * I.N + p] = Y;
+    const T X = step_normal<T>(a, i, gp, tag);
+    colloc<T, NET>(a, I, Y, hA, hB, y, mask);
+    Y = basis<T>(a, X, y, L);
+    if (clamp && Y < T(0)) Y = T(0);
+  }
+  const T K = sizeof(T) == 8 ? (T)I.K : (T)I.K_f;
+  const double f = a.payoff == 0 ? (double)Y : fmax((double)Y - (double)K, 0.0);
+  T lam = a.payoff == 0 ? T(1) : (Y > K ? T(1) : T(0));
+  double thb[4] = {0, 0, 0, 0};
+  const int nseg = (M + k - 1) / k;
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int i0 = seg * k, i1 = min(i0 + k, M);
+    T Yc = valid ? ck[(int64_t)seg * I.N + p] : (T)I.Y0;
+    for (int i = i0; i < i1; ++i) {
+      ybuf[(i - i0) * 64] = Yc;
+      if (i + 1 < i1) {
+        const T X = step_normal<T>(a, i, gp, tag);
+        colloc<T, NET>(a, I, Yc, hA, hB, y, mask);
+        Yc = basis<T>(a, X, y, L);
+        if (clamp && Yc < T(0)) Yc = T(0);
+      }
+    }
+    for (int i = i1 - 1; i >= i0; --i) {
+      const T Yi = ybuf[(i - i0) * 64];
+      const T X = step_normal<T>(a, i, gp, tag);
+      colloc<T, NET>(a, I, Yi, hA, hB, y, mask);
+      const T g = basis<T>(a, X, y, L);
+      const bool pass = !(clamp && g < T(0));
+#pragma unroll
+      for (int j = 0; j < kMaxM; ++j) ybar[j] = pass ? lam * L[j] : T(0);
+      lam = vjp<T, NET>(a, I, Yi, ybar, mask, hA, hB, thb);
+    }
+  }
+  // per-path outputs: f, dY0, dtheta
+  const int nq = 2 + a.n_theta;
+  double q[6] = {f, (double)lam, thb[0], thb[1], thb[2], thb[3]};
+  if (!valid)
+    for (int t = 0; t < 6; ++t) q[t] = 0.0;
+  if (a.per_path && valid)
+    for (int t = 0; t < nq; ++t) a.per_path[p * nq + t] = q[t];
+  double s[6], s2[6];
+  for (int t = 0; t < 6; ++t) {
+    s[t] = q[t];
+    s2[t] = q[t] * q[t];
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1)
+    for (int t = 0; t < 6; ++t) {
+      s[t] += __shfl_xor(s[t], off);
+      s2[t] += __shfl_xor(s2[t], off);
+    }
+  if (lane == 0) {
+    AdjPartial P;
+    for (int t = 0; t < 6; ++t) {
+      P.s[t] = s[t];
+      P.s2[t] = s2[t];
+    }
+    a.partials[blockIdx.x] = P;
+  }
+}
+
+// Fixed-order sum of the block partials: means and standard errors of f and
+// of every pathwise derivative.
+__global__ __launch_bounds__(256) void k_adjoint_finalize(const AdjPartial* __restrict__ parts,
+                                                          int64_t nb, int64_t N,
+                                                          double* __restrict__ out) {
+  __shared__ double sh[12][256];
+  double acc[12];
+  for (int t = 0; t < 12; ++t) acc[t] = 0.0;
+  for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
+    const AdjPartial q = parts[b];
+    for (int t = 0; t < 6; ++t) {
+      acc[t] += q.s[t];
+      acc[6 + t] += q.s2[t];
+    }
+  }
+  for (int t = 0; t < 12; ++t) sh[t][threadIdx.x] = acc[t];
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int t = 0; t < 12; ++t) sh[t][threadIdx.x] += sh[t][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double n = (double)N;
+    for (int t = 0; t < 6; ++t) {
+      const double mean = sh[t][0] / n;
+      const double var = N > 1 ? fmax(sh[6 + t][0] - sh[t][0] * mean, 0.0) / (n - 1.0) : 0.0;
+      out[t] = mean;
+      out[6 + t] = sqrt(var / n);
+    }
+  }
+}
+
+size_t adjoint_lds_bytes(int prec, int ckpt) {
+  const size_t el = prec == SL7_F64 ? sizeof(double) : sizeof(float);
+  return el * (2 * 64 * 64 + (size_t)ckpt * 64);
+}
+
+hipError_t launch_adjoint(int prec, int use_net, const AdjArgs& a, int64_t n_blocks,
+                          hipStream_t s) {
+  const size_t lds = adjoint_lds_bytes(prec, a.ckpt);
+  const void* fn;
+  if (prec == SL7_F64) fn = use_net ? (const void*)k_adjoint<double, true> : (const void*)k_adjoint<double, false>;
+  else fn = use_net ? (const void*)k_adjoint<float, true> : (const void*)k_adjoint<float, false>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  dim3 grid((unsigned)n_blocks), block(64);
+  if (prec == SL7_F64) {
+    if (use_net) hipLaunchKernelGGL((k_adjoint<double, true>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((k_adjoint<double, false>), grid, block, lds, s, a);
+  } else {
+    if (use_net) hipLaunchKernelGGL((k_adjoint<float, true>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((k_adjoint<float, false>), grid, block, lds, s, a);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_adjoint_finalize, dim3(1), dim3(256), 0, s, a.partials, n_blocks,
+                     a.inst_N, a.result);
+  return hipGetLastError();
+}
+
+}  // namespace sl7

@@ -1,0 +1,33 @@
+// Kernel arguments of the adjoint sweep.
+#pragma once
+
+#include "sl7_internal.hpp"
+
+namespace sl7 {
+
+struct AdjPartial {
+  double s[6], s2[6];  // sums of f, dY0, dtheta_0..3 and of their squares
+};
+
+struct AdjArgs {
+  const InstDev* inst;
+  int64_t inst_N;
+  int32_t m, n_theta, ckpt, payoff;
+  const void* net;     // lane layout of the network (T), NULL for the analytic map
+  const void* c0;      // first-layer constant of the instance (T, device)
+  const void* wtheta;  // [n_theta x 64] first-layer weight of theta_k times its scale (T)
+  void* ckpt_buf;      // [ceil(M/ckpt) x N] states (T)
+  AdjPartial* partials;
+  double* result;      // [12]: means then standard errors
+  double* per_path;    // NULL or [N x (2 + n_theta)]
+  uint64_t seed;
+  float xs[kMaxM], ls[kMaxM];
+  double xd[kMaxM], ld[kMaxM];
+  double dA[4][kMaxM], dB[4][kMaxM];  // analytic map: d(A_j, B_j)/dtheta_k
+};
+
+size_t adjoint_lds_bytes(int prec, int ckpt);
+hipError_t launch_adjoint(int prec, int use_net, const AdjArgs& a, int64_t n_blocks,
+                          hipStream_t s);
+
+}  // namespace sl7

@@ -55,12 +55,14 @@ struct Mlp {
   int device = -1;
   std::unique_ptr<DevBuf> pack[6];  // MFMA register layouts, by precision
   std::unique_ptr<DevBuf> net64, w0full, w0n, c0n;
+  std::unique_ptr<DevBuf> net32, wth64, wth32;  // adjoint lane layouts
 
   void layout();
   float W(int l, int o, int k) const;
   float b(int l, int o) const;
   void drop_device();
   int ensure_device(int prec);
+  int ensure_adjoint(int prec);
 };
 
 int64_t n_params_of(const sl7_mlp_desc& d);
