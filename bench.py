@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WEIGHTS = os.path.join(ROOT, "tests", "golden", "gbm_mlp_4x64.sl7w")
+CIR_WEIGHTS = os.path.join(ROOT, "tests", "golden", "cir_mlp_5x64.sl7w")
 FLOPS_PER_PATH_STEP = 2 * (4 * 64 + 3 * 64 * 64 + 64 * 5)  # 25,728
 PEAK = {"bf16": 2.5e15, "f16": 2.5e15, "bf16x3": 2.5e15, "f16x3": 2.5e15, "f32": 157.3e12,
         "f64": 78.6e12}
@@ -97,6 +98,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-paths", type=int, default=2 ** 14)
+    ap.add_argument("--profile-run", default=None,
+                    help="only run the default workload in this precision (plus a 256 MiB "
+                         "calibration copy) for rocprofv3; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -117,6 +121,17 @@ def main():
     c = W.CONFIGS["c2"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
     ps = c["N"] * c["M"]
+    if args.profile_run:
+        src = torch.ones(2 ** 26, dtype=torch.float32, device="cuda")  # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {src.numel() * 4} bytes read and written")
+        for _ in range(args.steps):
+            S.simulate(pr, H, prec=args.profile_run, seed=c["seed"], stats=True)
+        torch.cuda.synchronize()
+        log(f"profile run: {args.steps} launches of {args.profile_run}, N={c['N']}, M={c['M']}")
+        return
     res = {}
     for prec, steps in (("bf16x3", args.steps), ("bf16", args.steps),
                         ("f16x3", max(3, args.steps // 2)), ("f16", max(3, args.steps // 2)),
@@ -133,6 +148,50 @@ def main():
     pr1 = S.Problem(c1["model"], c1["theta"], c1["Y0"], c1["T"], c1["M"], c1["m"], c1["N"], K=c1["K"])
     wall1, _, st1 = time_calls(S, pr1, H, "f32", c1["seed"], max(2, args.steps // 2), 1, stats=True)
     log(f"c1 f32: {c1['N'] * c1['M'] / wall1:.3e} path-steps/s")
+
+    # adjoint: pathwise Greeks of E[max(Y_T - 1, 0)] for the N = 2^22, M = 16 workload
+    c3 = W.CONFIGS["c3"]
+    pr3 = S.Problem(c3["model"], c3["theta"], c3["Y0"], c3["T"], c3["M"], c3["m"], c3["N"], K=c3["K"])
+    adj = {}
+    for prec in ("f64", "f32"):
+        S.adjoint(pr3, H, prec=prec, seed=c3["seed"], payoff=1, ckpt_every=c3["ckpt"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = S.adjoint(pr3, H, prec=prec, seed=c3["seed"], payoff=1, ckpt_every=c3["ckpt"])
+        dt = time.perf_counter() - t0
+        adj[prec] = {"s_per_greek": dt / len(g["grad"]), "seconds": dt, "greeks": g["grad"],
+                     "greeks_se": g["grad_se"]}
+        log(f"adjoint {prec}: {dt:.3f} s for {len(g['grad'])} Greeks {g['grad']}")
+
+    # batched: 256 uneven CIR instances in one persistent launch, graph replays
+    Hc = S.Mlp.load(CIR_WEIGHTS)
+    prs = [S.Problem(d["model"], d["theta"], d["Y0"], d["T"], d["M"], d["m"], d["N"],
+                     K=d["theta"][1], instance=d["instance"]) for d in W.cir_instances(256)]
+    ps4 = sum(p.N * p.M for p in prs)
+    batched = {}
+    for prec in ("bf16x3", "bf16", "f32"):
+        S.simulate_batched(prs, Hc, prec=prec, seed=11, use_graph=True)
+        reps = 5 if prec != "f32" else 2
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            S.simulate_batched(prs, Hc, prec=prec, seed=11, use_graph=True)
+        dt = (time.perf_counter() - t0) / reps
+        batched[prec] = {"path_steps_per_s": ps4 / dt, "ms_per_launch": dt * 1e3}
+        log(f"batched {prec}: {ps4 / dt:.3e} path-steps/s ({dt * 1e3:.2f} ms per replay)")
+
+    # trainer: one epoch over 2^16 labels, batch 1024
+    feats = torch.tensor(W.gbm_features(W.N_LABELS), dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    labs = S.labels(W.GBM, 5, feats, n_paths=W.LABEL_PATHS, substeps=W.LABEL_SUBSTEPS,
+                    seed=W.TRAIN_SEED)
+    torch.cuda.synchronize()
+    t_lab = time.perf_counter() - t0
+    Ht = S.Mlp.load(WEIGHTS)
+    S.train(Ht, feats, labs, epochs=1)
+    t0 = time.perf_counter()
+    S.train(Ht, feats, labs, epochs=2)
+    t_ep = (time.perf_counter() - t0) / 2
+    log(f"labels {t_lab:.2f} s for 2^16 x 10^4 x 100 EM steps; train {t_ep * 1e3:.1f} ms per epoch")
 
     b = res["bf16x3"]
     t_kernel = b["ev_async"]
@@ -167,6 +226,10 @@ def main():
         "bf16x3_minus_f32_mean_over_se": (b["st"]["mean"][0] - res["f32"]["st"]["mean"][0]) / se_pair,
         "speedup_vs_f32_mfma": res["f32"]["wall"] / b["wall"],
         "c1_f32_path_steps_per_s": c1["N"] * c1["M"] / wall1,
+        "adjoint_c3": adj,
+        "batched_c4": dict(batched, instances=len(prs), path_steps=ps4),
+        "offline": {"labels_s": t_lab, "label_em_steps": W.N_LABELS * W.LABEL_PATHS * W.LABEL_SUBSTEPS,
+                    "train_ms_per_step": t_ep * 1e3 / (W.N_LABELS // W.BATCH)},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, Ho, c["seed"], args.cpu_paths)

@@ -1,0 +1,114 @@
+"""Batched uneven CIR instances (one persistent launch, longest-M-first work
+queue, hipGraph replays) and the launch-plan autotuner.
+
+Each instance's statistics from the batched launch must equal, bit for bit,
+those of a single-instance launch of the same instance (same kernel, same
+fixed-order 64-path block sums); single-instance runs are in turn checked
+path by path against the oracle.  CIR per-path error is measured against
+max(|Y|, 1e-3 ybar) (the law has mass near 0).
+"""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CIR_WEIGHTS = os.path.join(ROOT, "tests", "golden", "cir_mlp_5x64.sl7w")
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_2302_05170_amd as S
+    assert torch.cuda.is_available()
+    return S
+
+
+@pytest.fixture(scope="module")
+def H(S):
+    return S.Mlp.load(CIR_WEIGHTS)
+
+
+def problems(S, n=256, scale=1.0):
+    out = []
+    for d in W.cir_instances(n):
+        out.append(S.Problem(d["model"], d["theta"], d["Y0"], d["T"], d["M"], d["m"],
+                             max(1, int(d["N"] * scale)), K=d["theta"][1], instance=d["instance"]))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "f32", "bf16"])
+def test_batched_equals_single_instance_runs(S, H, prec):
+    prs = problems(S, 40, scale=0.25)
+    got = S.simulate_batched(prs, H, prec=prec, seed=11, use_graph=False)
+    for k, pr in enumerate(prs):
+        st, _ = S.simulate(pr, H, prec=prec, seed=11)
+        assert got[k] == st, k
+
+
+def test_batched_graph_replays_match_eager(S, H):
+    prs = problems(S, 64, scale=0.2)
+    ref = S.simulate_batched(prs, H, prec="bf16x3", seed=11, use_graph=False)
+    for r in range(3):
+        got = S.simulate_batched(prs, H, prec="bf16x3", seed=11, use_graph=True)
+        assert got == ref, r
+        # eager work on the same device between replays
+        S.simulate(prs[r], H, prec="f32", seed=5)
+        torch.cuda.synchronize()
+
+
+def test_batched_result_independent_of_instance_order(S, H):
+    prs = problems(S, 32, scale=0.2)
+    a = S.simulate_batched(prs, H, prec="bf16x3", seed=11, use_graph=False)
+    perm = np.random.default_rng(0).permutation(len(prs))
+    b = S.simulate_batched([prs[i] for i in perm], H, prec="bf16x3", seed=11, use_graph=False)
+    for j, i in enumerate(perm):
+        assert b[j] == a[i]
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5), ("bf16x3", 2e-3)])
+def test_cir_instances_match_oracle(S, H, prec, tol):
+    Ho = oracle.load_mlp(CIR_WEIGHTS)
+    prs = problems(S, 256)
+    for k in (0, 7, 100, 255):
+        pr = prs[k]
+        pr = S.Problem(pr.model, pr.theta, pr.Y0, pr.T, pr.M, pr.m, min(pr.N, 3000), K=pr.K,
+                       instance=pr.instance)
+        st, yt = S.simulate(pr, H, prec=prec, seed=11, want_yt=True)
+        torch.cuda.synchronize()
+        y = yt.double().cpu().numpy()
+        opr = oracle.Problem(pr.model, pr.theta, pr.Y0, pr.T, pr.M, pr.m, pr.instance)
+        ref, ncl, nood = oracle.simulate(opr, Ho, 11, np.arange(pr.N))
+        err = np.abs(y - ref) / np.maximum(np.abs(ref), 1e-3 * pr.theta[1])
+        print(f"instance {k} {prec}: max err {err.max():.2e}, clamped {st['n_clamped']} (oracle {ncl})")
+        assert err.max() <= tol
+        if prec == "f64":
+            assert st["n_clamped"] == ncl and st["n_out_of_domain"] == nood
+
+
+def test_autotune_returns_valid_plan_and_caches(S, H):
+    import ctypes
+    from paper_2302_05170_amd import _lib as L
+    pr = problems(S, 1)[0]
+    pr = S.Problem(pr.model, pr.theta, pr.Y0, pr.T, 16, 7, 2 ** 16, K=pr.K)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "plans.jsonl").encode()
+        plan = L.Plan()
+        cp = pr.c()
+        L.check(L.lib().sl7_autotune(ctypes.byref(cp), H.handle, L.BF16X3, path, ctypes.byref(plan),
+                                     None))
+        assert plan.waves_per_block in (1, 2, 4) and 1 <= plan.blocks_per_cu <= 8
+        text = open(path).read()
+        assert '"key": "gfx950/prec4/din5/m7"' in text
+        plan2 = L.Plan()
+        L.check(L.lib().sl7_autotune(ctypes.byref(cp), H.handle, L.BF16X3, path, ctypes.byref(plan2),
+                                     None))
+        assert (plan2.waves_per_block, plan2.blocks_per_cu, plan2.grab) == \
+            (plan.waves_per_block, plan.blocks_per_cu, plan.grab)
+        assert open(path).read() == text  # second call read the cache
