@@ -225,5 +225,6 @@ def test_eval_H_matches_oracle_forward(S, H, Ho, prec):
     # on the same rounded inputs
     ref = Ho.forward(x.astype(np.float32).astype(np.float64))
     # outputs are FP32 in every mode
-    tol = {"f64": 1.2e-7, "f32": 1e-5, "bf16": 2e-2, "f16": 5e-3, "bf16x3": 1e-5, "f16x3": 1e-5}[prec]
+    # (the split BF16 form drops lo*lo, ~2^-16 of each product)
+    tol = {"f64": 1.2e-7, "f32": 1e-5, "bf16": 2e-2, "f16": 5e-3, "bf16x3": 1e-4, "f16x3": 1e-5}[prec]
     assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 0.1)) <= tol
