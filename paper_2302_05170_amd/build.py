@@ -17,8 +17,11 @@ LIB = os.path.join(HERE, "libsl7.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-# Packed FP32 VALU forms are kept out of the generated code.
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Packed FP32 VALU forms are kept out of the generated code.  MFMA results and
+# accumulator inputs are kept in VGPRs (the fused kernels' epilogues read them
+# with VALU instructions; accumulators in AGPRs would cost a copy per value).
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-mllvm", "-amdgpu-mfma-vgpr-form"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
           "-Wno-unused-function", "-I", os.path.join(os.path.dirname(HERE), "include")]
 

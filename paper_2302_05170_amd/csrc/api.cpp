@@ -455,6 +455,8 @@ void fill_inst(const sl7_problem& pr, const Mlp* H, const double* x, InstDev& I)
   I.Y0_f = (float)pr.Y0;
   I.dom_lo = -INFINITY;
   I.dom_hi = INFINITY;
+  I.dom_lo_f = -INFINITY;
+  I.dom_hi_f = INFINITY;
   if (!H) {
     if (pr.model == SL7_GBM) {
       const double sig = pr.theta[0], mu = pr.theta[1];
@@ -475,6 +477,12 @@ void fill_inst(const sl7_problem& pr, const Mlp* H, const double* x, InstDev& I)
   }
   I.dom_lo = H->d.dom_lo[0];
   I.dom_hi = H->d.dom_hi[0];
+  // smallest float >= dom_lo and largest float <= dom_hi: for a float Y,
+  // Y < dom_lo iff Y < dom_lo_f, and Y > dom_hi iff Y > dom_hi_f
+  I.dom_lo_f = (float)I.dom_lo;
+  if ((double)I.dom_lo_f < I.dom_lo) I.dom_lo_f = std::nextafter(I.dom_lo_f, INFINITY);
+  I.dom_hi_f = (float)I.dom_hi;
+  if ((double)I.dom_hi_f > I.dom_hi) I.dom_hi_f = std::nextafter(I.dom_hi_f, -INFINITY);
   double in[SL7_MAX_DIN] = {0.0, dt};
   for (int k = 0; k < n_theta(pr.model); ++k) in[2 + k] = pr.theta[k];
   for (int o = 0; o < kWidth; ++o) {
@@ -510,7 +518,7 @@ int fill_nodes(int m, SimArgs& a, double* x_out) {
 
 int default_plan(int prec, sl7_plan* p) {
   p->waves_per_block = 4;
-  p->blocks_per_cu = (prec == SL7_BF16 || prec == SL7_F16) ? 2 : 1;  // register-limited occupancy
+  p->blocks_per_cu = is_half(prec) ? 2 : 1;  // register-limited occupancy
   p->grab = 1;
   p->reserved = 0;
   return SL7_OK;

@@ -67,16 +67,38 @@ __device__ __forceinline__ typename H16<P>::v8 pack8(f32x4 lo, f32x4 hi) {
   return __builtin_bit_cast(typename H16<P>::v8, w);
 }
 
+// Biases (the accumulator inputs of the MFMA chains) live in LDS, one copy
+// per workgroup laid out [slot][lane]: each lane reads its own 16 bytes right
+// before use, so the accumulators and their inputs stay in VGPRs.
+struct BiasLds {
+  const f32x4* p;  // 13 slots: hidden [3][4], head
+  // Keeps the bias reads inside the step loop (otherwise the compiler hoists
+  // them into registers, which then have to be copied into the accumulators).
+  static __device__ __forceinline__ void pin() { asm volatile("" ::: "memory"); }
+  __device__ __forceinline__ f32x4 hid(int l, int b, int lane) const { return p[(4 * l + b) * 64 + lane]; }
+  __device__ __forceinline__ f32x4 head(int lane) const { return p[12 * 64 + lane]; }
+};
+
+// Copies the 13 bias slots (starting at slot s0 of the packed weights) into
+// LDS; every wave of the workgroup must call it.
+__device__ __forceinline__ BiasLds stage_bias(const u32x4* __restrict__ wp, int s0, f32x4* lds) {
+  for (int i = threadIdx.x; i < 13 * 64; i += blockDim.x)
+    lds[i] = __builtin_bit_cast(f32x4, wp[s0 * 64 + i]);
+  __syncthreads();
+  return BiasLds{lds};
+}
+
 template <int P>
 struct NetRegsH {
   typedef typename H16<P>::v8 v8;
   v8 A[3][4][2];  // hidden layers: [layer][out block][K block]
   v8 Ah[2];       // head: [K block]
-  f32x4 C[3][4];  // hidden biases (accumulator input)
-  f32x4 Ch;       // head bias
   f32x4 wY[4];    // first-layer weight of Y (times its input scale)
+  BiasLds C;      // hidden and head biases
+  int lane;
 
-  __device__ __forceinline__ void load(const u32x4* __restrict__ wp, int lane) {
+  __device__ __forceinline__ void load(const u32x4* __restrict__ wp, int ln, f32x4* lds) {
+    lane = ln;
     int s = 0;
 #pragma unroll
     for (int l = 0; l < 3; ++l)
@@ -86,11 +108,8 @@ struct NetRegsH {
         for (int c = 0; c < 2; ++c) A[l][b][c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
 #pragma unroll
     for (int c = 0; c < 2; ++c) Ah[c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
-#pragma unroll
-    for (int l = 0; l < 3; ++l)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) C[l][b] = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
-    Ch = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
+    C = stage_bias(wp, s, lds);
+    s += 13;
 #pragma unroll
     for (int b = 0; b < 4; ++b) wY[b] = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
   }
@@ -99,17 +118,18 @@ struct NetRegsH {
 template <int P>
 __device__ __forceinline__ f32x4 chain_h(const NetRegsH<P>& R, typename H16<P>::v8 B0,
                                          typename H16<P>::v8 B1) {
+  BiasLds::pin();
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
     f32x4 acc[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[b] = H16<P>::mfma(R.A[l][b][0], B0, R.C[l][b]);
+    for (int b = 0; b < 4; ++b) acc[b] = H16<P>::mfma(R.A[l][b][0], B0, R.C.hid(l, b, R.lane));
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[b] = H16<P>::mfma(R.A[l][b][1], B1, acc[b]);
     B0 = pack8<P>(acc[0], acc[1]);
     B1 = pack8<P>(acc[2], acc[3]);
   }
-  f32x4 y = H16<P>::mfma(R.Ah[0], B0, R.Ch);
+  f32x4 y = H16<P>::mfma(R.Ah[0], B0, R.C.head(R.lane));
   return H16<P>::mfma(R.Ah[1], B1, y);
 }
 
@@ -137,21 +157,45 @@ struct Split16<SL7_F16X3> {
   static constexpr int base = SL7_F16;
 };
 
-// ReLU in FP32, then the (hi, lo) pair of B operands for eight activations.
+// ReLU on a float through its bit pattern: a negative float is a negative
+// 32-bit integer, so a signed max with 0 gives +0 (no NaN canonicalisation).
+__device__ __forceinline__ float relu_bits(float x) {
+  return __builtin_bit_cast(float, __builtin_elementwise_max(__builtin_bit_cast(int, x), 0));
+}
+
+// The (hi, lo) pair of B operands for eight activations, ReLU applied.
+// BF16: hi is the activation truncated to its upper 16 bits and lo = x - hi
+// (exact in FP32, then rounded to BF16); hi and lo carry the sign of x, so
+// ReLU is a signed 16-bit max of the packed halves.  FP16: ReLU in FP32, hi
+// rounded to nearest, lo = x - hi rounded to nearest.
 template <int P>
 __device__ __forceinline__ void split8(f32x4 a, f32x4 b, typename Split16<P>::v8& hi,
                                        typename Split16<P>::v8& lo) {
   typedef typename Split16<P>::v2 v2;
-  const float v[8] = {fmaxf(a[0], 0.f), fmaxf(a[1], 0.f), fmaxf(a[2], 0.f), fmaxf(a[3], 0.f),
-                      fmaxf(b[0], 0.f), fmaxf(b[1], 0.f), fmaxf(b[2], 0.f), fmaxf(b[3], 0.f)};
+  const float v[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
   u32x4 wh, wl;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const v2 h = __builtin_convertvector((f32x2){v[2 * q], v[2 * q + 1]}, v2);
-    const f32x2 back = __builtin_convertvector(h, f32x2);
-    const v2 l = __builtin_convertvector((f32x2){v[2 * q] - back[0], v[2 * q + 1] - back[1]}, v2);
-    wh[q] = __builtin_bit_cast(uint32_t, h);
-    wl[q] = __builtin_bit_cast(uint32_t, l);
+    if constexpr (P == SL7_BF16X3) {
+      const uint32_t u0 = __builtin_bit_cast(uint32_t, v[2 * q]);
+      const uint32_t u1 = __builtin_bit_cast(uint32_t, v[2 * q + 1]);
+      const float l0 = v[2 * q] - __builtin_bit_cast(float, u0 & 0xffff0000u);
+      const float l1 = v[2 * q + 1] - __builtin_bit_cast(float, u1 & 0xffff0000u);
+      // upper halves of u0 (low result half) and u1 (high result half)
+      const uint32_t h = __builtin_amdgcn_perm(u1, u0, 0x07060302u);
+      const v2 l = __builtin_convertvector((f32x2){l0, l1}, v2);
+      const s16x2 hs = __builtin_elementwise_max(__builtin_bit_cast(s16x2, h), (s16x2){0, 0});
+      const s16x2 ls = __builtin_elementwise_max(__builtin_bit_cast(s16x2, l), (s16x2){0, 0});
+      wh[q] = __builtin_bit_cast(uint32_t, hs);
+      wl[q] = __builtin_bit_cast(uint32_t, ls);
+    } else {
+      const float x0 = relu_bits(v[2 * q]), x1 = relu_bits(v[2 * q + 1]);
+      const v2 h = __builtin_convertvector((f32x2){x0, x1}, v2);
+      const f32x2 back = __builtin_convertvector(h, f32x2);
+      const v2 l = __builtin_convertvector((f32x2){x0 - back[0], x1 - back[1]}, v2);
+      wh[q] = __builtin_bit_cast(uint32_t, h);
+      wl[q] = __builtin_bit_cast(uint32_t, l);
+    }
   }
   hi = __builtin_bit_cast(typename Split16<P>::v8, wh);
   lo = __builtin_bit_cast(typename Split16<P>::v8, wl);
@@ -160,13 +204,23 @@ __device__ __forceinline__ void split8(f32x4 a, f32x4 b, typename Split16<P>::v8
 template <int P>
 struct NetRegsX3 {
   typedef typename Split16<P>::v8 v8;
-  v8 A[3][4][2], Al[3][4][2];
-  v8 Ah[2], Ahl[2];
-  f32x4 C[3][4];
-  f32x4 Ch;
+  v8 A[3][4][2];        // hi parts of the hidden-layer weights
+  v8 Ah[2];             // hi parts of the head weights
   f32x4 wY[4];
+  BiasLds C;
+  const u32x4* lo;      // LDS: lo parts, hidden [3][4][2] then head [2], [slot][lane]
+  int lane;
 
-  __device__ __forceinline__ void load(const u32x4* __restrict__ wp, int lane) {
+  __device__ __forceinline__ v8 Al(int l, int b, int c) const {
+    return __builtin_bit_cast(v8, lo[((l * 4 + b) * 2 + c) * 64 + lane]);
+  }
+  __device__ __forceinline__ v8 Ahl(int c) const {
+    return __builtin_bit_cast(v8, lo[(24 + c) * 64 + lane]);
+  }
+
+  __device__ __forceinline__ void load(const u32x4* __restrict__ wp, int ln, f32x4* lds,
+                                       u32x4* lo_lds) {
+    lane = ln;
     int s = 0;
 #pragma unroll
     for (int l = 0; l < 3; ++l)
@@ -176,26 +230,19 @@ struct NetRegsX3 {
         for (int c = 0; c < 2; ++c) A[l][b][c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
 #pragma unroll
     for (int c = 0; c < 2; ++c) Ah[c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
-#pragma unroll
-    for (int l = 0; l < 3; ++l)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) C[l][b] = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
-    Ch = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
+    const int s_bias = s;
+    s += 13;
 #pragma unroll
     for (int b = 0; b < 4; ++b) wY[b] = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
-#pragma unroll
-    for (int l = 0; l < 3; ++l)
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) Al[l][b][c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
-#pragma unroll
-    for (int c = 0; c < 2; ++c) Ahl[c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
+    for (int i = threadIdx.x; i < 26 * 64; i += blockDim.x) lo_lds[i] = wp[s * 64 + i];
+    lo = lo_lds;
+    C = stage_bias(wp, s_bias, lds);  // synchronises the workgroup
   }
 };
 
 template <int P>
 __device__ __forceinline__ f32x4 chain_x3(const NetRegsX3<P>& R, const f32x4 z[4]) {
+  BiasLds::pin();
   typedef typename Split16<P>::v8 v8;
   constexpr int B = Split16<P>::base;
   v8 h0, h1, l0, l1;
@@ -205,9 +252,9 @@ __device__ __forceinline__ f32x4 chain_x3(const NetRegsX3<P>& R, const f32x4 z[4
   for (int l = 0; l < 3; ++l) {
     f32x4 acc[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.Al[l][b][0], h0, R.C[l][b]);
+    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.Al(l, b, 0), h0, R.C.hid(l, b, R.lane));
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.Al[l][b][1], h1, acc[b]);
+    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.Al(l, b, 1), h1, acc[b]);
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.A[l][b][0], l0, acc[b]);
 #pragma unroll
@@ -219,8 +266,8 @@ __device__ __forceinline__ f32x4 chain_x3(const NetRegsX3<P>& R, const f32x4 z[4
     split8<P>(acc[0], acc[1], h0, l0);
     split8<P>(acc[2], acc[3], h1, l1);
   }
-  f32x4 y = H16<B>::mfma(R.Ahl[0], h0, R.Ch);
-  y = H16<B>::mfma(R.Ahl[1], h1, y);
+  f32x4 y = H16<B>::mfma(R.Ahl(0), h0, R.C.head(R.lane));
+  y = H16<B>::mfma(R.Ahl(1), h1, y);
   y = H16<B>::mfma(R.Ah[0], l0, y);
   y = H16<B>::mfma(R.Ah[1], l1, y);
   y = H16<B>::mfma(R.Ah[0], h0, y);
@@ -234,11 +281,12 @@ __device__ __forceinline__ f32x4 chain_x3(const NetRegsX3<P>& R, const f32x4 z[4
 struct NetRegsF {
   float A[3][4][16];
   float Ah[16];
-  f32x4 C[3][4];
-  f32x4 Ch;
   f32x4 wY[4];
+  BiasLds C;
+  int lane;
 
-  __device__ __forceinline__ void load(const u32x4* __restrict__ wp, int lane) {
+  __device__ __forceinline__ void load(const u32x4* __restrict__ wp, int ln, f32x4* lds) {
+    lane = ln;
     int s = 0;
 #pragma unroll
     for (int l = 0; l < 3; ++l)
@@ -256,24 +304,23 @@ struct NetRegsF {
 #pragma unroll
       for (int e = 0; e < 4; ++e) Ah[4 * q + e] = v[e];
     }
-#pragma unroll
-    for (int l = 0; l < 3; ++l)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) C[l][b] = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
-    Ch = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
+    C = stage_bias(wp, s, lds);
+    s += 13;
 #pragma unroll
     for (int b = 0; b < 4; ++b) wY[b] = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
   }
 };
 
 __device__ __forceinline__ f32x4 relu4(f32x4 v) {
-  return (f32x4){fmaxf(v[0], 0.f), fmaxf(v[1], 0.f), fmaxf(v[2], 0.f), fmaxf(v[3], 0.f)};
+  return (f32x4){relu_bits(v[0]), relu_bits(v[1]), relu_bits(v[2]), relu_bits(v[3])};
 }
 
 __device__ __forceinline__ f32x4 chain_f(const NetRegsF& R, f32x4 Bv[4]) {
+  BiasLds::pin();
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
-    f32x4 acc[4] = {R.C[l][0], R.C[l][1], R.C[l][2], R.C[l][3]};
+    f32x4 acc[4] = {R.C.hid(l, 0, R.lane), R.C.hid(l, 1, R.lane), R.C.hid(l, 2, R.lane),
+                    R.C.hid(l, 3, R.lane)};
 #pragma unroll
     for (int kb = 0; kb < 16; ++kb)
 #pragma unroll
@@ -283,7 +330,7 @@ __device__ __forceinline__ f32x4 chain_f(const NetRegsF& R, f32x4 Bv[4]) {
 #pragma unroll
     for (int b = 0; b < 4; ++b) Bv[b] = relu4(acc[b]);
   }
-  f32x4 y = R.Ch;
+  f32x4 y = R.C.head(R.lane);
 #pragma unroll
   for (int kb = 0; kb < 16; ++kb)
     y = __builtin_amdgcn_mfma_f32_16x16x4f32(R.Ah[kb], Bv[kb >> 2][kb & 3], y, 0, 0, 0);
@@ -291,33 +338,29 @@ __device__ __forceinline__ f32x4 chain_f(const NetRegsF& R, f32x4 Bv[4]) {
 }
 
 // ------------------------------------------------------------------------
-// Barycentric interpolation over the lane's rows 4g..4g+3 of the head tile.
-// xr/lr: this lane's nodes and weights (1e30 / 0 for rows >= m).
+// Barycentric interpolation over the lane's rows 4g..4g+3 of the head tile
+// (second form).  xr/lr: this lane's nodes and weights (1e30 / 0 for rows
+// >= m).  At a node, X - x_j == 0 is replaced by 1e-30: that node's weight
+// then exceeds the others by ~28 orders of magnitude and the quotient is y_j
+// to FP32 rounding, without a branch.  Two xor-shuffles complete the sums of
+// the path's four lanes in the same order on each of them.
 // ------------------------------------------------------------------------
 __device__ __forceinline__ float interp_rows(float X, f32x4 yv, const float xr[4],
-                                             const float lr[4], const SimArgs& a, int m) {
-  bool anyhit = false;
-#pragma unroll
-  for (int j = 0; j < kMaxM; ++j)
-    if (j < m && X == a.xs[j]) anyhit = true;
-  float num = 0.f, den = 0.f, yh = 0.f;
-  bool own = false;
+                                             const float lr[4]) {
+  float num = 0.f, den = 0.f;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const float t = lr[r] * fast_rcp(X - xr[r]);
+    float d = X - xr[r];
+    d = d == 0.f ? 1e-30f : d;
+    const float t = lr[r] * fast_rcp(d);
     num = fmaf(t, yv[r], num);
     den += t;
-    if (X == xr[r]) { own = true; yh = yv[r]; }
-  }
-  if (anyhit) {
-    num = own ? yh : 0.f;
-    den = own ? 1.f : 0.f;
   }
   num += __shfl_xor(num, 16);
   den += __shfl_xor(den, 16);
   num += __shfl_xor(num, 32);
   den += __shfl_xor(den, 32);
-  return num / den;
+  return num * fast_rcp(den);
 }
 
 __device__ __forceinline__ void lane_rows(const SimArgs& a, int m, int g, float xr[4],
@@ -366,10 +409,9 @@ __device__ __forceinline__ void sim_block(const SimArgs& a, const InstDev& I, in
                                           const Net& net, const float xr[4], const float lr[4],
                                           int lane, int g, int n) {
   const int M = I.M;
-  const int m = a.m;
   const uint32_t tag = (uint32_t)I.tag;
   const bool clamp = I.clamp_zero != 0;
-  const double dlo = I.dom_lo, dhi = I.dom_hi;
+  const float dlo = I.dom_lo_f, dhi = I.dom_hi_f;
   f32x4 c0[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) c0[b] = *(const f32x4*)(I.c0 + 16 * b + 4 * g);
@@ -389,9 +431,9 @@ __device__ __forceinline__ void sim_block(const SimArgs& a, const InstDev& I, in
       for (int u = 0; u < 4; ++u) {
         if (i0 + u < M) {
           const float X = __shfl(xc[u], src);
-          if (g == t && ((double)Y < dlo || (double)Y > dhi)) ++ood;
+          if (g == t && (Y < dlo || Y > dhi)) ++ood;
           const f32x4 yv = net.eval(Y, c0);
-          Y = interp_rows(X, yv, xr, lr, a, m);
+          Y = interp_rows(X, yv, xr, lr);
           if (clamp && Y < 0.f) {
             Y = 0.f;
             if (g == t) ++clamped;
@@ -429,7 +471,7 @@ struct NetF {
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Bv[b][r] = fmaxf(fmaf(Y, R.wY[b][r], c0[b][r]), 0.f);
+      for (int r = 0; r < 4; ++r) Bv[b][r] = relu_bits(fmaf(Y, R.wY[b][r], c0[b][r]));
     return chain_f(R, Bv);
   }
 };
@@ -468,21 +510,25 @@ __device__ __forceinline__ void sim_persistent(const SimArgs& a, const Net& net)
 template <int P>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_sim_mfma_h(SimArgs a) {
+  __shared__ f32x4 bias_lds[13 * 64];
   NetH<P> net;
-  net.R.load((const u32x4*)a.wpack, threadIdx.x & 63);
+  net.R.load((const u32x4*)a.wpack, threadIdx.x & 63, bias_lds);
   sim_persistent(a, net);
 }
 
 template <int P>
 __global__ __launch_bounds__(256) void k_sim_mfma_x3(SimArgs a) {
+  __shared__ f32x4 bias_lds[13 * 64];
+  __shared__ u32x4 lo_lds[26 * 64];
   NetX3<P> net;
-  net.R.load((const u32x4*)a.wpack, threadIdx.x & 63);
+  net.R.load((const u32x4*)a.wpack, threadIdx.x & 63, bias_lds, lo_lds);
   sim_persistent(a, net);
 }
 
 __global__ __launch_bounds__(256) void k_sim_mfma_f(SimArgs a) {
+  __shared__ f32x4 bias_lds[13 * 64];
   NetF net;
-  net.R.load((const u32x4*)a.wpack, threadIdx.x & 63);
+  net.R.load((const u32x4*)a.wpack, threadIdx.x & 63, bias_lds);
   sim_persistent(a, net);
 }
 
@@ -556,8 +602,9 @@ template <int P>
 __global__ __launch_bounds__(256) void k_eval_mfma_h(const void* wpack, const float* w0n,
                                                      const float* c0n, int d_in, int m,
                                                      const float* in, int64_t B, float* out) {
+  __shared__ f32x4 bias_lds[13 * 64];
   NetHz<P> net;
-  net.R.load((const u32x4*)wpack, threadIdx.x & 63);
+  net.R.load((const u32x4*)wpack, threadIdx.x & 63, bias_lds);
   eval_rows(net, w0n, c0n, d_in, m, in, B, out);
 }
 
@@ -565,16 +612,19 @@ template <int P>
 __global__ __launch_bounds__(256) void k_eval_mfma_x3(const void* wpack, const float* w0n,
                                                       const float* c0n, int d_in, int m,
                                                       const float* in, int64_t B, float* out) {
+  __shared__ f32x4 bias_lds[13 * 64];
+  __shared__ u32x4 lo_lds[26 * 64];
   NetX3<P> net;
-  net.R.load((const u32x4*)wpack, threadIdx.x & 63);
+  net.R.load((const u32x4*)wpack, threadIdx.x & 63, bias_lds, lo_lds);
   eval_rows(net, w0n, c0n, d_in, m, in, B, out);
 }
 
 __global__ __launch_bounds__(256) void k_eval_mfma_f(const void* wpack, const float* w0n,
                                                      const float* c0n, int d_in, int m,
                                                      const float* in, int64_t B, float* out) {
+  __shared__ f32x4 bias_lds[13 * 64];
   NetFz net;
-  net.R.load((const u32x4*)wpack, threadIdx.x & 63);
+  net.R.load((const u32x4*)wpack, threadIdx.x & 63, bias_lds);
   eval_rows(net, w0n, c0n, d_in, m, in, B, out);
 }
 

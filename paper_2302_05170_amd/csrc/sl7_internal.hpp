@@ -25,6 +25,8 @@ struct alignas(16) InstDev {
   int32_t M, m, model, tag;
   int32_t clamp_zero;   // 1: Y <- max(Y, 0) after each step (CIR)
   float K_f, Y0_f, dt_f;
+  float dom_lo_f, dom_hi_f;  // float Y is out of domain iff Y < dom_lo_f or Y > dom_hi_f
+  int32_t pad_[2];
   double K, Y0, dt, dom_lo, dom_hi;
   double A[kMaxM], B[kMaxM];  // analytic map: y_j = A_j * Y + B_j
   alignas(16) float c0[kWidth]; // network: first-layer constant (dt, theta folded)
