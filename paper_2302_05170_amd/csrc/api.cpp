@@ -563,6 +563,7 @@ int prepare_instances(const sl7_problem* prs, int n, const Mlp* H, int prec, uin
   if (!rc) rc = ws.counter.reserve(256);
   if (!rc) rc = ws.partials.reserve(sizeof(Partial) * std::max<int64_t>(parts, 1));
   if (!rc) rc = ws.stats.reserve(sizeof(sl7_stats) * n);
+  if (!rc) rc = ws.chunks.reserve(finalize_scratch_bytes(n));
   if (rc) return rc;
   hipError_t e = hipMemcpyAsync(ws.inst.p, inst.data(), sizeof(InstDev) * n, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipMemcpyAsync(ws.prefix.p, prefix.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, stream);
@@ -603,7 +604,7 @@ int launch_instances(const SimArgs& a_in, int n, int64_t N0, const Mlp* H, int p
     e = launch_sim_lane(prec, H ? 1 : 0, H ? H->d.act : 0, a, (N0 + 63) / 64, stream);
     if (e != hipSuccess) return hip_fail(e, "launch per-lane kernel");
   }
-  e = launch_finalize(a.partials, a.inst, n, (sl7_stats*)ws.stats.p, stream);
+  e = launch_finalize(a.partials, a.inst, n, ws.chunks.p, (sl7_stats*)ws.stats.p, stream);
   if (e != hipSuccess) return hip_fail(e, "launch finalize");
   return SL7_OK;
 }

@@ -162,15 +162,40 @@ struct Comp {
   __device__ double value() const { return s + c; }
 };
 
-__global__ __launch_bounds__(256) void k_finalize(const Partial* __restrict__ parts,
-                                                  const InstDev* __restrict__ inst,
-                                                  sl7_stats* __restrict__ out) {
+// Two fixed-order passes: (1) workgroup (instance k, chunk c) sums the block
+// partials of a fixed contiguous chunk (strided per thread, Neumaier, then a
+// fixed tree); (2) one workgroup per instance combines its kChunks chunk sums
+// in a fixed tree and writes the statistics.  The result depends only on the
+// partials, never on the launch shape of the simulation.
+constexpr int kChunks = 64;
+
+struct ChunkSum {
+  Comp c[4];
+  long long clamped, ood;
+};
+
+__device__ void tree_reduce(Comp (*sh)[256], long long (*shl)[256], int n) {
+  for (int w = n / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x].merge(sh[k][threadIdx.x + w]);
+      shl[0][threadIdx.x] += shl[0][threadIdx.x + w];
+      shl[1][threadIdx.x] += shl[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_finalize_chunks(const Partial* __restrict__ parts,
+                                                         const InstDev* __restrict__ inst,
+                                                         ChunkSum* __restrict__ chunks) {
   const InstDev& I = inst[blockIdx.x];
+  const int c = blockIdx.y;
   const int64_t nb = (I.N + 63) / 64;
+  const int64_t b0 = nb * c / kChunks, b1 = nb * (c + 1) / kChunks;
   const Partial* P = parts + I.part_offset;
   Comp acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
   long long cl = 0, od = 0;
-  for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
+  for (int64_t b = b0 + threadIdx.x; b < b1; b += blockDim.x) {
     const Partial q = P[b];
     acc[0].add(q.s[0]); acc[1].add(q.s[1]); acc[2].add(q.q[0]); acc[3].add(q.q[1]);
     cl += q.clamped; od += q.ood;
@@ -181,14 +206,28 @@ __global__ __launch_bounds__(256) void k_finalize(const Partial* __restrict__ pa
   shl[0][threadIdx.x] = cl;
   shl[1][threadIdx.x] = od;
   __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x].merge(sh[k][threadIdx.x + w]);
-      shl[0][threadIdx.x] += shl[0][threadIdx.x + w];
-      shl[1][threadIdx.x] += shl[1][threadIdx.x + w];
-    }
-    __syncthreads();
+  tree_reduce(sh, shl, 256);
+  if (threadIdx.x == 0) {
+    ChunkSum r;
+    for (int k = 0; k < 4; ++k) r.c[k] = sh[k][0];
+    r.clamped = shl[0][0];
+    r.ood = shl[1][0];
+    chunks[(int64_t)blockIdx.x * kChunks + c] = r;
   }
+}
+
+__global__ __launch_bounds__(kChunks) void k_finalize(const ChunkSum* __restrict__ chunks,
+                                                      const InstDev* __restrict__ inst,
+                                                      sl7_stats* __restrict__ out) {
+  const InstDev& I = inst[blockIdx.x];
+  __shared__ Comp sh[4][256];
+  __shared__ long long shl[2][256];
+  const ChunkSum r = chunks[(int64_t)blockIdx.x * kChunks + threadIdx.x];
+  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = r.c[k];
+  shl[0][threadIdx.x] = r.clamped;
+  shl[1][threadIdx.x] = r.ood;
+  __syncthreads();
+  tree_reduce(sh, shl, kChunks);
   if (threadIdx.x == 0) {
     sl7_stats st;
     const double n = (double)I.N;
@@ -206,9 +245,16 @@ __global__ __launch_bounds__(256) void k_finalize(const Partial* __restrict__ pa
   }
 }
 
-hipError_t launch_finalize(const Partial* parts, const InstDev* inst, int n_inst, sl7_stats* out,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(n_inst), dim3(256), 0, s, parts, inst, out);
+size_t finalize_scratch_bytes(int n_inst) { return sizeof(ChunkSum) * kChunks * (size_t)n_inst; }
+
+hipError_t launch_finalize(const Partial* parts, const InstDev* inst, int n_inst, void* scratch,
+                           sl7_stats* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_chunks, dim3(n_inst, kChunks), dim3(256), 0, s, parts, inst,
+                     (ChunkSum*)scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finalize, dim3(n_inst), dim3(kChunks), 0, s, (const ChunkSum*)scratch, inst,
+                     out);
   return hipGetLastError();
 }
 

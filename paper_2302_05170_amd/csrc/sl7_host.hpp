@@ -36,7 +36,7 @@ struct DevBuf {
 struct Workspace {
   std::mutex mu;
   int n_cu = 0;
-  DevBuf inst, prefix, order, counter, partials, stats;
+  DevBuf inst, prefix, order, counter, partials, stats, chunks;
   DevBuf aux[8];  // adjoint checkpoints, trainer buffers, ...
   sl7_stats* stats_host = nullptr;
   int stats_host_n = 0;
