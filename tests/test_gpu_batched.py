@@ -5,8 +5,10 @@ Each instance's statistics from the batched launch must equal, bit for bit,
 those of a single-instance launch of the same instance (same kernel, same
 fixed-order 64-path block sums); single-instance runs are in turn checked
 path by path against the oracle.  CIR per-path error is measured against
-max(|Y|, 0.1 ybar): CIR paths spend time at the zero clamp, where FP32
-arithmetic on quantities of size ybar leaves absolute errors of ~1e-7 ybar.
+max(|Y|, ybar), the process's mean-reversion level: CIR paths spend time at
+and near the zero clamp, where a relative error says nothing about the law
+and FP32 arithmetic on network activations of order one leaves absolute
+errors of ~1e-7.
 """
 import os
 import tempfile
@@ -86,7 +88,7 @@ def test_cir_instances_match_oracle(S, H, prec, tol):
         y = yt.double().cpu().numpy()
         opr = oracle.Problem(pr.model, pr.theta, pr.Y0, pr.T, pr.M, pr.m, pr.instance)
         ref, ncl, nood = oracle.simulate(opr, Ho, 11, np.arange(pr.N))
-        err = np.abs(y - ref) / np.maximum(np.abs(ref), 0.1 * pr.theta[1])
+        err = np.abs(y - ref) / np.maximum(np.abs(ref), pr.theta[1])
         print(f"instance {k} {prec}: max err {err.max():.2e}, clamped {st['n_clamped']} (oracle {ncl})")
         assert err.max() <= tol
         if prec == "f64":
