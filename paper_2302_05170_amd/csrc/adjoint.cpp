@@ -121,6 +121,7 @@ extern "C" int sl7_adjoint(const sl7_problem* pr, const sl7_mlp* Hc, int prec, u
   if (ckpt_every < 1 || ckpt_every > 32) return fail(SL7_EINVAL, "ckpt_every=%d outside [1, 32]", ckpt_every);
   if (!out) return fail(SL7_EINVAL, "out is NULL");
   if (!ws_dev) return fail(SL7_EINVAL, "ws_dev is NULL");
+  if (H && H->d.act != SL7_RELU) return fail(SL7_EUNSUPPORTED, "the adjoint back-propagates ReLU networks only");
   const WsLayout Lw = layout_of(pr, prec, ckpt_every);
   if (ws_bytes < Lw.total) return fail(SL7_EINVAL, "ws_bytes=%zu < %zu needed", ws_bytes, Lw.total);
   if (H) {

@@ -190,12 +190,20 @@ void Mlp::layout() {
   }
 }
 
+// Weights and biases with zero padding: units beyond the network's width (or
+// outputs beyond m) read as 0, so a narrower network runs in the 64-wide
+// kernels unchanged (a padded unit's outgoing weights are all zero).
 float Mlp::W(int l, int o, int k) const {
   const int in = (l == 0) ? d.d_in : d.width;
+  const int out = (l == d.depth) ? d.m : d.width;
+  if (o >= out || k >= in) return 0.f;
   return params[W_off[l] + (int64_t)o * in + k];
 }
 
-float Mlp::b(int l, int o) const { return params[b_off[l] + o]; }
+float Mlp::b(int l, int o) const {
+  const int out = (l == d.depth) ? d.m : d.width;
+  return o < out ? params[b_off[l] + o] : 0.f;
+}
 
 void Mlp::drop_device() {
   for (auto& p : pack) p.reset();
@@ -429,10 +437,9 @@ int check_problem(const sl7_problem* pr, const Mlp* H, int prec, const char* nam
     if (H->d.d_in != 2 + n_theta(pr->model))
       return fail(SL7_EINVAL, "%s: model needs d_in=%d, network has %d", name, 2 + n_theta(pr->model), H->d.d_in);
     if (H->d.model != pr->model) return fail(SL7_EINVAL, "%s.model=%d but the network was built for model %d", name, pr->model, H->d.model);
-    if (H->d.width != kWidth || H->d.depth != SL7_DEPTH)
-      return fail(SL7_EUNSUPPORTED, "network %dx%d: kernels need width %d, depth %d", H->d.depth, H->d.width, kWidth, SL7_DEPTH);
-    if (prec != SL7_F64 && H->d.act != SL7_RELU)
-      return fail(SL7_EUNSUPPORTED, "softplus networks run in F64 only");
+    if (H->d.width > kWidth || H->d.depth != SL7_DEPTH)
+      return fail(SL7_EUNSUPPORTED, "network %dx%d: kernels need width <= %d and depth %d", H->d.depth,
+                  H->d.width, kWidth, SL7_DEPTH);
   }
   return SL7_OK;
 }
@@ -596,7 +603,7 @@ int launch_instances(const SimArgs& a_in, int n, int64_t N0, const Mlp* H, int p
     e = launch_zero_u64(a.counter, 1, stream);
     if (e != hipSuccess) return hip_fail(e, "zero counter");
     const int grid = plan.blocks_per_cu * ws.n_cu;
-    e = launch_sim_mfma(prec, a, grid, plan.waves_per_block, stream);
+    e = launch_sim_mfma(prec, H->d.act, a, grid, plan.waves_per_block, stream);
     if (e != hipSuccess) return hip_fail(e, "launch fused MFMA kernel");
   } else {
     if (n != 1) return fail(SL7_EUNSUPPORTED, "batched launches need a network in F32/BF16/F16");
@@ -720,9 +727,8 @@ int sl7_eval_H(const sl7_mlp* Hc, int prec, const float* in_dev, int64_t B, floa
   if (B < 0) return fail(SL7_EINVAL, "B=%lld must be >= 0", (long long)B);
   if (B > 0 && (!in_dev || !out_dev)) return fail(SL7_EINVAL, "in_dev and out_dev must be non-NULL");
   Mlp* H = const_cast<Mlp*>(reinterpret_cast<const Mlp*>(Hc));
-  if (H->d.width != kWidth || H->d.depth != SL7_DEPTH)
-    return fail(SL7_EUNSUPPORTED, "kernels need width %d and depth %d", kWidth, SL7_DEPTH);
-  if (prec != SL7_F64 && H->d.act != SL7_RELU) return fail(SL7_EUNSUPPORTED, "softplus networks run in F64 only");
+  if (H->d.width > kWidth || H->d.depth != SL7_DEPTH)
+    return fail(SL7_EUNSUPPORTED, "kernels need width <= %d and depth %d", kWidth, SL7_DEPTH);
   int rc = H->ensure_device(prec);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
@@ -731,7 +737,7 @@ int sl7_eval_H(const sl7_mlp* Hc, int prec, const float* in_dev, int64_t B, floa
     e = launch_eval_lane((const double*)H->net64->p, (const double*)H->w0full->p, H->d.d_in, H->d.m,
                          H->d.act, in_dev, B, out_dev, s);
   else
-    e = launch_eval_mfma(prec, H->pack[prec]->p, (const float*)H->w0n->p, (const float*)H->c0n->p,
+    e = launch_eval_mfma(prec, H->d.act, H->pack[prec]->p, (const float*)H->w0n->p, (const float*)H->c0n->p,
                          H->d.d_in, H->d.m, in_dev, B, out_dev, s);
   if (e != hipSuccess) return hip_fail(e, "launch eval_H");
   return SL7_OK;

@@ -24,6 +24,24 @@
 
 namespace sl7 {
 
+// ReLU on a float through its bit pattern: a negative float is a negative
+// 32-bit integer, so a signed max with 0 gives +0 (no NaN canonicalisation).
+__device__ __forceinline__ float relu_bits(float x) {
+  return __builtin_bit_cast(float, __builtin_elementwise_max(__builtin_bit_cast(int, x), 0));
+}
+
+// Softplus log(1 + e^z) = max(z, 0) + log(1 + e^{-|z|}) on the
+// transcendental unit (base-2 exp and log).
+__device__ __forceinline__ float softplus_f(float z) {
+  const float u = __builtin_amdgcn_exp2f(-fabsf(z) * 1.44269504088896341f);
+  return relu_bits(z) + __builtin_amdgcn_logf(1.f + u) * 0.693147180559945309f;
+}
+
+template <int ACT>
+__device__ __forceinline__ float act_f(float z) {
+  if constexpr (ACT == SL7_RELU) return relu_bits(z); else return softplus_f(z);
+}
+
 // ------------------------------------------------------------------------
 // BF16 / FP16 operands (v_mfma_f32_16x16x32_{bf16,f16}).
 // ------------------------------------------------------------------------
@@ -33,6 +51,7 @@ struct H16;
 template <>
 struct H16<SL7_BF16> {
   typedef bf16x8 v8;
+  typedef __bf16 elem;
   static __device__ __forceinline__ f32x4 mfma(v8 a, v8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
@@ -48,6 +67,7 @@ struct H16<SL7_BF16> {
 template <>
 struct H16<SL7_F16> {
   typedef f16x8 v8;
+  typedef _Float16 elem;
   static __device__ __forceinline__ f32x4 mfma(v8 a, v8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
@@ -59,11 +79,22 @@ struct H16<SL7_F16> {
 };
 
 // Eight activations (units 4g..4g+3 of two consecutive 16-unit blocks) as
-// one K=32 B operand.
-template <int P>
+// one K=32 B operand.  ReLU is applied to the packed halves; Softplus in FP32
+// before the conversion.
+template <int P, int ACT>
 __device__ __forceinline__ typename H16<P>::v8 pack8(f32x4 lo, f32x4 hi) {
-  const u32x4 w = {H16<P>::pack_relu(lo[0], lo[1]), H16<P>::pack_relu(lo[2], lo[3]),
-                   H16<P>::pack_relu(hi[0], hi[1]), H16<P>::pack_relu(hi[2], hi[3])};
+  u32x4 w;
+  if constexpr (ACT == SL7_RELU) {
+    w = (u32x4){H16<P>::pack_relu(lo[0], lo[1]), H16<P>::pack_relu(lo[2], lo[3]),
+                H16<P>::pack_relu(hi[0], hi[1]), H16<P>::pack_relu(hi[2], hi[3])};
+  } else {
+    typedef __attribute__((ext_vector_type(2))) typename H16<P>::elem e2;
+    const float v[8] = {softplus_f(lo[0]), softplus_f(lo[1]), softplus_f(lo[2]), softplus_f(lo[3]),
+                        softplus_f(hi[0]), softplus_f(hi[1]), softplus_f(hi[2]), softplus_f(hi[3])};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      w[q] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){v[2 * q], v[2 * q + 1]}, e2));
+  }
   return __builtin_bit_cast(typename H16<P>::v8, w);
 }
 
@@ -115,7 +146,7 @@ struct NetRegsH {
   }
 };
 
-template <int P>
+template <int P, int ACT>
 __device__ __forceinline__ f32x4 chain_h(const NetRegsH<P>& R, typename H16<P>::v8 B0,
                                          typename H16<P>::v8 B1) {
   BiasLds::pin();
@@ -126,8 +157,8 @@ __device__ __forceinline__ f32x4 chain_h(const NetRegsH<P>& R, typename H16<P>::
     for (int b = 0; b < 4; ++b) acc[b] = H16<P>::mfma(R.A[l][b][0], B0, R.C.hid(l, b, R.lane));
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[b] = H16<P>::mfma(R.A[l][b][1], B1, acc[b]);
-    B0 = pack8<P>(acc[0], acc[1]);
-    B1 = pack8<P>(acc[2], acc[3]);
+    B0 = pack8<P, ACT>(acc[0], acc[1]);
+    B1 = pack8<P, ACT>(acc[2], acc[3]);
   }
   f32x4 y = H16<P>::mfma(R.Ah[0], B0, R.C.head(R.lane));
   return H16<P>::mfma(R.Ah[1], B1, y);
@@ -157,22 +188,20 @@ struct Split16<SL7_F16X3> {
   static constexpr int base = SL7_F16;
 };
 
-// ReLU on a float through its bit pattern: a negative float is a negative
-// 32-bit integer, so a signed max with 0 gives +0 (no NaN canonicalisation).
-__device__ __forceinline__ float relu_bits(float x) {
-  return __builtin_bit_cast(float, __builtin_elementwise_max(__builtin_bit_cast(int, x), 0));
-}
-
 // The (hi, lo) pair of B operands for eight activations, ReLU applied.
 // BF16: hi is the activation truncated to its upper 16 bits and lo = x - hi
 // (exact in FP32, then rounded to BF16); hi and lo carry the sign of x, so
 // ReLU is a signed 16-bit max of the packed halves.  FP16: ReLU in FP32, hi
 // rounded to nearest, lo = x - hi rounded to nearest.
-template <int P>
+template <int P, int ACT>
 __device__ __forceinline__ void split8(f32x4 a, f32x4 b, typename Split16<P>::v8& hi,
                                        typename Split16<P>::v8& lo) {
   typedef typename Split16<P>::v2 v2;
-  const float v[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+  float v[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+  if constexpr (ACT != SL7_RELU) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = softplus_f(v[i]);  // >= 0: the ReLU below is a no-op
+  }
   u32x4 wh, wl;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -240,14 +269,14 @@ struct NetRegsX3 {
   }
 };
 
-template <int P>
+template <int P, int ACT>
 __device__ __forceinline__ f32x4 chain_x3(const NetRegsX3<P>& R, const f32x4 z[4]) {
   BiasLds::pin();
   typedef typename Split16<P>::v8 v8;
   constexpr int B = Split16<P>::base;
   v8 h0, h1, l0, l1;
-  split8<P>(z[0], z[1], h0, l0);
-  split8<P>(z[2], z[3], h1, l1);
+  split8<P, ACT>(z[0], z[1], h0, l0);
+  split8<P, ACT>(z[2], z[3], h1, l1);
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
     f32x4 acc[4];
@@ -263,8 +292,8 @@ __device__ __forceinline__ f32x4 chain_x3(const NetRegsX3<P>& R, const f32x4 z[4
     for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.A[l][b][0], h0, acc[b]);
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.A[l][b][1], h1, acc[b]);
-    split8<P>(acc[0], acc[1], h0, l0);
-    split8<P>(acc[2], acc[3], h1, l1);
+    split8<P, ACT>(acc[0], acc[1], h0, l0);
+    split8<P, ACT>(acc[2], acc[3], h1, l1);
   }
   f32x4 y = H16<B>::mfma(R.Ahl(0), h0, R.C.head(R.lane));
   y = H16<B>::mfma(R.Ahl(1), h1, y);
@@ -311,10 +340,12 @@ struct NetRegsF {
   }
 };
 
-__device__ __forceinline__ f32x4 relu4(f32x4 v) {
-  return (f32x4){relu_bits(v[0]), relu_bits(v[1]), relu_bits(v[2]), relu_bits(v[3])};
+template <int ACT>
+__device__ __forceinline__ f32x4 act4(f32x4 v) {
+  return (f32x4){act_f<ACT>(v[0]), act_f<ACT>(v[1]), act_f<ACT>(v[2]), act_f<ACT>(v[3])};
 }
 
+template <int ACT>
 __device__ __forceinline__ f32x4 chain_f(const NetRegsF& R, f32x4 Bv[4]) {
   BiasLds::pin();
 #pragma unroll
@@ -328,7 +359,7 @@ __device__ __forceinline__ f32x4 chain_f(const NetRegsF& R, f32x4 Bv[4]) {
         acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(R.A[l][b][kb], Bv[kb >> 2][kb & 3], acc[b],
                                                       0, 0, 0);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) Bv[b] = relu4(acc[b]);
+    for (int b = 0; b < 4; ++b) Bv[b] = act4<ACT>(acc[b]);
   }
   f32x4 y = R.C.head(R.lane);
 #pragma unroll
@@ -451,7 +482,7 @@ __device__ __forceinline__ void sim_block(const SimArgs& a, const InstDev& I, in
   block_partial(f0, f1, valid ? clamped : 0, valid ? ood : 0, a.partials + I.part_offset + blk);
 }
 
-template <int P>
+template <int P, int ACT>
 struct NetH {
   NetRegsH<P> R;
   __device__ __forceinline__ f32x4 eval(float Y, const f32x4 c0[4]) const {
@@ -460,10 +491,14 @@ struct NetH {
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) z[b][r] = fmaf(Y, R.wY[b][r], c0[b][r]);
-    return chain_h<P>(R, pack8<P>(z[0], z[1]), pack8<P>(z[2], z[3]));
+    return chain_h<P, ACT>(R, pack8<P, ACT>(z[0], z[1]), pack8<P, ACT>(z[2], z[3]));
+  }
+  __device__ __forceinline__ f32x4 eval_z0(const f32x4 z[4]) const {
+    return chain_h<P, ACT>(R, pack8<P, ACT>(z[0], z[1]), pack8<P, ACT>(z[2], z[3]));
   }
 };
 
+template <int ACT>
 struct NetF {
   NetRegsF R;
   __device__ __forceinline__ f32x4 eval(float Y, const f32x4 c0[4]) const {
@@ -471,12 +506,16 @@ struct NetF {
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Bv[b][r] = relu_bits(fmaf(Y, R.wY[b][r], c0[b][r]));
-    return chain_f(R, Bv);
+      for (int r = 0; r < 4; ++r) Bv[b][r] = act_f<ACT>(fmaf(Y, R.wY[b][r], c0[b][r]));
+    return chain_f<ACT>(R, Bv);
+  }
+  __device__ __forceinline__ f32x4 eval_z0(const f32x4 z[4]) const {
+    f32x4 Bv[4] = {act4<ACT>(z[0]), act4<ACT>(z[1]), act4<ACT>(z[2]), act4<ACT>(z[3])};
+    return chain_f<ACT>(R, Bv);
   }
 };
 
-template <int P>
+template <int P, int ACT>
 struct NetX3 {
   NetRegsX3<P> R;
   __device__ __forceinline__ f32x4 eval(float Y, const f32x4 c0[4]) const {
@@ -485,9 +524,9 @@ struct NetX3 {
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) z[b][r] = fmaf(Y, R.wY[b][r], c0[b][r]);
-    return chain_x3<P>(R, z);
+    return chain_x3<P, ACT>(R, z);
   }
-  __device__ __forceinline__ f32x4 eval_z0(const f32x4 z[4]) const { return chain_x3<P>(R, z); }
+  __device__ __forceinline__ f32x4 eval_z0(const f32x4 z[4]) const { return chain_x3<P, ACT>(R, z); }
 };
 
 template <class Net>
@@ -507,39 +546,46 @@ __device__ __forceinline__ void sim_persistent(const SimArgs& a, const Net& net)
   }
 }
 
-template <int P>
+template <int P, int ACT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_sim_mfma_h(SimArgs a) {
   __shared__ f32x4 bias_lds[13 * 64];
-  NetH<P> net;
+  NetH<P, ACT> net;
   net.R.load((const u32x4*)a.wpack, threadIdx.x & 63, bias_lds);
   sim_persistent(a, net);
 }
 
-template <int P>
+template <int P, int ACT>
 __global__ __launch_bounds__(256) void k_sim_mfma_x3(SimArgs a) {
   __shared__ f32x4 bias_lds[13 * 64];
   __shared__ u32x4 lo_lds[26 * 64];
-  NetX3<P> net;
+  NetX3<P, ACT> net;
   net.R.load((const u32x4*)a.wpack, threadIdx.x & 63, bias_lds, lo_lds);
   sim_persistent(a, net);
 }
 
+template <int ACT>
 __global__ __launch_bounds__(256) void k_sim_mfma_f(SimArgs a) {
   __shared__ f32x4 bias_lds[13 * 64];
-  NetF net;
+  NetF<ACT> net;
   net.R.load((const u32x4*)a.wpack, threadIdx.x & 63, bias_lds);
   sim_persistent(a, net);
 }
 
-hipError_t launch_sim_mfma(int prec, const SimArgs& a, int grid, int waves_per_block,
+template <int ACT>
+static void launch_sim_mfma_act(int prec, const SimArgs& a, dim3 g, dim3 b, hipStream_t s) {
+  if (prec == SL7_BF16) hipLaunchKernelGGL((k_sim_mfma_h<SL7_BF16, ACT>), g, b, 0, s, a);
+  else if (prec == SL7_F16) hipLaunchKernelGGL((k_sim_mfma_h<SL7_F16, ACT>), g, b, 0, s, a);
+  else if (prec == SL7_BF16X3) hipLaunchKernelGGL((k_sim_mfma_x3<SL7_BF16X3, ACT>), g, b, 0, s, a);
+  else if (prec == SL7_F16X3) hipLaunchKernelGGL((k_sim_mfma_x3<SL7_F16X3, ACT>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_sim_mfma_f<ACT>), g, b, 0, s, a);
+}
+
+hipError_t launch_sim_mfma(int prec, int act, const SimArgs& a, int grid, int waves_per_block,
                            hipStream_t s) {
   dim3 g(grid), b(64 * waves_per_block);
-  if (prec == SL7_BF16) hipLaunchKernelGGL(k_sim_mfma_h<SL7_BF16>, g, b, 0, s, a);
-  else if (prec == SL7_F16) hipLaunchKernelGGL(k_sim_mfma_h<SL7_F16>, g, b, 0, s, a);
-  else if (prec == SL7_BF16X3) hipLaunchKernelGGL(k_sim_mfma_x3<SL7_BF16X3>, g, b, 0, s, a);
-  else if (prec == SL7_F16X3) hipLaunchKernelGGL(k_sim_mfma_x3<SL7_F16X3>, g, b, 0, s, a);
-  else hipLaunchKernelGGL(k_sim_mfma_f, g, b, 0, s, a);
+  if (act == SL7_RELU) launch_sim_mfma_act<SL7_RELU>(prec, a, g, b, s);
+  else launch_sim_mfma_act<SL7_SOFTPLUS>(prec, a, g, b, s);
   return hipGetLastError();
 }
 
@@ -584,66 +630,62 @@ __device__ __forceinline__ void eval_rows(const Net& net, const float* __restric
   }
 }
 
-template <int P>
-struct NetHz : NetH<P> {
-  __device__ __forceinline__ f32x4 eval_z0(const f32x4 z[4]) const {
-    return chain_h<P>(this->R, pack8<P>(z[0], z[1]), pack8<P>(z[2], z[3]));
-  }
-};
-
-struct NetFz : NetF {
-  __device__ __forceinline__ f32x4 eval_z0(const f32x4 z[4]) const {
-    f32x4 Bv[4] = {relu4(z[0]), relu4(z[1]), relu4(z[2]), relu4(z[3])};
-    return chain_f(R, Bv);
-  }
-};
-
-template <int P>
+template <int P, int ACT>
 __global__ __launch_bounds__(256) void k_eval_mfma_h(const void* wpack, const float* w0n,
                                                      const float* c0n, int d_in, int m,
                                                      const float* in, int64_t B, float* out) {
   __shared__ f32x4 bias_lds[13 * 64];
-  NetHz<P> net;
+  NetH<P, ACT> net;
   net.R.load((const u32x4*)wpack, threadIdx.x & 63, bias_lds);
   eval_rows(net, w0n, c0n, d_in, m, in, B, out);
 }
 
-template <int P>
+template <int P, int ACT>
 __global__ __launch_bounds__(256) void k_eval_mfma_x3(const void* wpack, const float* w0n,
                                                       const float* c0n, int d_in, int m,
                                                       const float* in, int64_t B, float* out) {
   __shared__ f32x4 bias_lds[13 * 64];
   __shared__ u32x4 lo_lds[26 * 64];
-  NetX3<P> net;
+  NetX3<P, ACT> net;
   net.R.load((const u32x4*)wpack, threadIdx.x & 63, bias_lds, lo_lds);
   eval_rows(net, w0n, c0n, d_in, m, in, B, out);
 }
 
+template <int ACT>
 __global__ __launch_bounds__(256) void k_eval_mfma_f(const void* wpack, const float* w0n,
                                                      const float* c0n, int d_in, int m,
                                                      const float* in, int64_t B, float* out) {
   __shared__ f32x4 bias_lds[13 * 64];
-  NetFz net;
+  NetF<ACT> net;
   net.R.load((const u32x4*)wpack, threadIdx.x & 63, bias_lds);
   eval_rows(net, w0n, c0n, d_in, m, in, B, out);
 }
 
-hipError_t launch_eval_mfma(int prec, const void* wpack, const float* w0n, const float* c0n,
-                            int d_in, int m, const float* in, int64_t B, float* out,
-                            hipStream_t s) {
+template <int ACT>
+static void launch_eval_act(int prec, dim3 g, const void* wpack, const float* w0n,
+                            const float* c0n, int d_in, int m, const float* in, int64_t B,
+                            float* out, hipStream_t s) {
+  const dim3 b(256);
+  if (prec == SL7_BF16)
+    hipLaunchKernelGGL((k_eval_mfma_h<SL7_BF16, ACT>), g, b, 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
+  else if (prec == SL7_F16)
+    hipLaunchKernelGGL((k_eval_mfma_h<SL7_F16, ACT>), g, b, 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
+  else if (prec == SL7_BF16X3)
+    hipLaunchKernelGGL((k_eval_mfma_x3<SL7_BF16X3, ACT>), g, b, 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
+  else if (prec == SL7_F16X3)
+    hipLaunchKernelGGL((k_eval_mfma_x3<SL7_F16X3, ACT>), g, b, 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
+  else
+    hipLaunchKernelGGL((k_eval_mfma_f<ACT>), g, b, 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
+}
+
+hipError_t launch_eval_mfma(int prec, int act, const void* wpack, const float* w0n,
+                            const float* c0n, int d_in, int m, const float* in, int64_t B,
+                            float* out, hipStream_t s) {
   if (B <= 0) return hipSuccess;
   const int64_t groups = (B + 15) / 16;
-  const int grid = (int)std::min<int64_t>((groups + 3) / 4, 2048);
-  if (prec == SL7_BF16)
-    hipLaunchKernelGGL(k_eval_mfma_h<SL7_BF16>, dim3(grid), dim3(256), 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
-  else if (prec == SL7_F16)
-    hipLaunchKernelGGL(k_eval_mfma_h<SL7_F16>, dim3(grid), dim3(256), 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
-  else if (prec == SL7_BF16X3)
-    hipLaunchKernelGGL(k_eval_mfma_x3<SL7_BF16X3>, dim3(grid), dim3(256), 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
-  else if (prec == SL7_F16X3)
-    hipLaunchKernelGGL(k_eval_mfma_x3<SL7_F16X3>, dim3(grid), dim3(256), 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
-  else
-    hipLaunchKernelGGL(k_eval_mfma_f, dim3(grid), dim3(256), 0, s, wpack, w0n, c0n, d_in, m, in, B, out);
+  const dim3 g((unsigned)std::min<int64_t>((groups + 3) / 4, 2048));
+  if (act == SL7_RELU) launch_eval_act<SL7_RELU>(prec, g, wpack, w0n, c0n, d_in, m, in, B, out, s);
+  else launch_eval_act<SL7_SOFTPLUS>(prec, g, wpack, w0n, c0n, d_in, m, in, B, out, s);
   return hipGetLastError();
 }
 

@@ -78,15 +78,15 @@ constexpr int kLaneNetDoubles(int m) { return 64 + 3 * (64 * 64 + 64) + 64 * m +
 // Launch helpers implemented in the .hip files.
 hipError_t launch_sim_lane(int prec, int use_net, int act, const SimArgs& a,
                            int64_t n_blocks, hipStream_t s);
-hipError_t launch_sim_mfma(int prec, const SimArgs& a, int grid, int waves_per_block,
+hipError_t launch_sim_mfma(int prec, int act, const SimArgs& a, int grid, int waves_per_block,
                            hipStream_t s);
 size_t finalize_scratch_bytes(int n_inst);
 hipError_t launch_finalize(const Partial* parts, const InstDev* inst, int n_inst, void* scratch,
                            sl7_stats* out, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
-hipError_t launch_eval_mfma(int prec, const void* wpack, const float* w0n,
-                            const float* c0n, int d_in, int m, const float* in,
-                            int64_t B, float* out, hipStream_t s);
+hipError_t launch_eval_mfma(int prec, int act, const void* wpack, const float* w0n,
+                            const float* c0n, int d_in, int m, const float* in, int64_t B,
+                            float* out, hipStream_t s);
 hipError_t launch_eval_lane(const double* net, const double* w0full, int d_in, int m,
                             int act, const float* in, int64_t B, float* out,
                             hipStream_t s);

@@ -9,6 +9,7 @@ section).  The result is rounded to FP32 when written.
 
     python tests/golden/make_weights.py gbm [--epochs 200]
     python tests/golden/make_weights.py cir [--epochs 200]
+    python tests/golden/make_weights.py ou  [--epochs 200]   (4 x 50 Softplus, EM labels)
 """
 import argparse
 import os
@@ -45,7 +46,7 @@ def cir_labels(features: np.ndarray, m: int) -> np.ndarray:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("model", choices=["gbm", "cir"])
+    ap.add_argument("model", choices=["gbm", "cir", "ou"])
     ap.add_argument("--epochs", type=int, default=200)
     ap.add_argument("--labels", type=int, default=W.N_LABELS)
     args = ap.parse_args()
@@ -56,6 +57,12 @@ def main():
         feats = W.gbm_features(args.labels)
         labels = oracle.em_labels(model, feats, m, W.LABEL_PATHS, W.LABEL_SUBSTEPS, seed=W.TRAIN_SEED)
         out = os.path.join(HERE, "gbm_mlp_4x64.sl7w")
+    elif args.model == "ou":
+        d_in, m, model = 5, 5, oracle.OU
+        lo, hi = W.OU_DOMAIN_LO, W.OU_DOMAIN_HI
+        feats = W.ou_features(args.labels)
+        labels = oracle.em_labels(model, feats, m, W.LABEL_PATHS, W.LABEL_SUBSTEPS, seed=W.TRAIN_SEED)
+        out = os.path.join(HERE, "ou_mlp_5x50_softplus.sl7w")
     else:
         d_in, m, model = 5, 7, oracle.CIR
         lo, hi = W.CIR_DOMAIN_LO, W.CIR_DOMAIN_HI
@@ -63,8 +70,10 @@ def main():
         labels = cir_labels(feats, m)
         out = os.path.join(HERE, "cir_mlp_5x64.sl7w")
     print(f"labels: {time.time() - t0:.1f} s", flush=True)
-    H0 = oracle.glorot_mlp(d_in, W.WIDTH, W.DEPTH, m, model, lo, hi,
-                           W.glorot_params(d_in, m, seed=W.TRAIN_SEED))
+    width = W.OU_WIDTH if args.model == "ou" else W.WIDTH
+    act = oracle.ACT_SOFTPLUS if args.model == "ou" else oracle.ACT_RELU
+    H0 = oracle.glorot_mlp(d_in, width, W.DEPTH, m, model, lo, hi,
+                           W.glorot_params(d_in, m, seed=W.TRAIN_SEED, width=width), act=act)
     order = W.minibatch_order(len(feats), args.epochs, seed=W.TRAIN_SEED)
     H, hist = oracle.train(H0, feats, labels, order, batch=W.BATCH, lr=1e-3, log_every=20)
     H = H.with_params(H.params_f32())

@@ -40,6 +40,12 @@ CONFIGS = {
 # Training domain of the GBM network, feature order (Y, dt, sigma, mu).
 GBM_DOMAIN_LO = np.array([0.5, 0.05, 0.1, 0.0])
 GBM_DOMAIN_HI = np.array([1.5, 0.5, 0.5, 0.2])
+# Training domain of the OU network (the paper's experiment, eq. 6.5), feature
+# order (Y, dt, ybar, sigma, lambda).
+OU_DOMAIN_LO = np.array([-1.0, 0.05, 0.0, 0.1, 0.5])
+OU_DOMAIN_HI = np.array([2.0, 0.5, 1.0, 0.5, 2.5])
+# The paper's network for OU: 4 hidden layers of 50 Softplus units.
+OU_WIDTH = 50
 # Training domain of the CIR network, feature order (Y, dt, kappa, ybar, gamma).
 CIR_DOMAIN_LO = np.array([0.0, 0.1, 0.5, 0.02, 0.1])
 CIR_DOMAIN_HI = np.array([1.3, 1.0, 3.0, 0.1, 0.5])
@@ -78,6 +84,18 @@ def gbm_features(n: int = N_LABELS, seed: int = TRAIN_SEED) -> np.ndarray:
     """Rows (Y, dt, sigma, mu) uniform over the GBM training domain."""
     rng = np.random.default_rng(seed + 1000)
     return rng.uniform(GBM_DOMAIN_LO, GBM_DOMAIN_HI, size=(n, 4))
+
+
+def ou_features(n: int = N_LABELS, seed: int = TRAIN_SEED) -> np.ndarray:
+    """Rows (Y, dt, ybar, sigma, lambda) uniform over the OU training domain."""
+    rng = np.random.default_rng(seed + 4000)
+    return rng.uniform(OU_DOMAIN_LO, OU_DOMAIN_HI, size=(n, 5))
+
+
+# The paper's OU experiment (Table 6.1) does not state T, M, theta or Y0;
+# these are this build's choice, with the paper's path counts.
+OU_PAPER = dict(model=OU, theta=(0.5, 0.3, 1.0), Y0=0.2, T=2.0, M=8, m=5, seed=42, K=0.5,
+                path_counts=(1_000, 50_000, 100_000, 200_000))
 
 
 def cir_features(n: int = N_LABELS, seed: int = TRAIN_SEED) -> np.ndarray:
