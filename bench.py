@@ -28,6 +28,11 @@ sys.path.insert(0, ROOT)
 
 WEIGHTS = os.path.join(ROOT, "tests", "golden", "gbm_mlp_4x64.sl7w")
 CIR_WEIGHTS = os.path.join(ROOT, "tests", "golden", "cir_mlp_5x64.sl7w")
+OU_WEIGHTS = os.path.join(ROOT, "tests", "golden", "ou_mlp_5x50_softplus.sl7w")
+# The paper's Table 6.1: 7L on OU with a 4x50 Softplus network, parallel time
+# (s) on an NVIDIA MX150 per path count.  Context only: another machine, and
+# the paper states neither T nor M.
+PAPER_T61_PARALLEL_S = {1_000: 0.268, 50_000: 6.844, 100_000: 14.623, 200_000: 21.545}
 FLOPS_PER_PATH_STEP = 2 * (4 * 64 + 3 * 64 * 64 + 64 * 5)  # 25,728
 PEAK = {"bf16": 2.5e15, "f16": 2.5e15, "bf16x3": 2.5e15, "f16x3": 2.5e15, "f32": 157.3e12,
         "f64": 78.6e12}
@@ -179,6 +184,22 @@ def main():
         batched[prec] = {"path_steps_per_s": ps4 / dt, "ms_per_launch": dt * 1e3}
         log(f"batched {prec}: {ps4 / dt:.3e} path-steps/s ({dt * 1e3:.2f} ms per replay)")
 
+    # the paper's OU experiment (eq. 6.5, 4x50 Softplus network) at the path
+    # counts of Table 6.1
+    ou = {}
+    if os.path.exists(OU_WEIGHTS):
+        Hou = S.Mlp.load(OU_WEIGHTS)
+        P = W.OU_PAPER
+        for prec in ("bf16x3", "f32"):
+            for n in P["path_counts"]:
+                pro = S.Problem(P["model"], P["theta"], P["Y0"], P["T"], P["M"], P["m"], n, K=P["K"])
+                wall_o, _, st_o = time_calls(S, pro, Hou, prec, P["seed"], 20, 2, stats=True)
+                ou.setdefault(prec, {})[str(n)] = {
+                    "ms_per_run": wall_o * 1e3, "path_steps_per_s": n * P["M"] / wall_o,
+                    "mean_YT": st_o["mean"][0], "paper_mx150_s": PAPER_T61_PARALLEL_S[n]}
+            log(f"OU 4x50 softplus {prec}: " + ", ".join(
+                f"N={k} {v['ms_per_run']:.3f} ms" for k, v in ou[prec].items()))
+
     # trainer: one epoch over 2^16 labels, batch 1024
     feats = torch.tensor(W.gbm_features(W.N_LABELS), dtype=torch.float32, device="cuda")
     t0 = time.perf_counter()
@@ -228,6 +249,9 @@ def main():
         "c1_f32_path_steps_per_s": c1["N"] * c1["M"] / wall1,
         "adjoint_c3": adj,
         "batched_c4": dict(batched, instances=len(prs), path_steps=ps4),
+        "ou_table61_shape": dict(ou, workload=f"OU theta={W.OU_PAPER['theta']}, Y0={W.OU_PAPER['Y0']}, "
+                                              f"T={W.OU_PAPER['T']}, M={W.OU_PAPER['M']}, m=5, "
+                                              "MLP 5-50x4-5 Softplus") if ou else None,
         "offline": {"labels_s": t_lab, "label_em_steps": W.N_LABELS * W.LABEL_PATHS * W.LABEL_SUBSTEPS,
                     "train_ms_per_step": t_ep * 1e3 / (W.N_LABELS // W.BATCH)},
     }
