@@ -33,8 +33,10 @@ struct alignas(16) InstDev {
   double c0d[kWidth];         // the same in FP64
 };
 
-// Sums over one 64-path block, reduced in a fixed order.
-struct alignas(16) Partial {
+// Sums over one 64-path block, reduced in a fixed order.  One record per
+// 64-byte line: the memory system writes whole lines, so a 48-byte record
+// that straddles two lines would cost two.
+struct alignas(64) Partial {
   double s[2], q[2];   // sum of f and f^2 for payoffs Y_T and (Y_T - K)^+
   long long clamped, ood;
 };
@@ -95,5 +97,5 @@ hipError_t launch_eval_lane(const double* net, const double* w0full, int d_in, i
 
 namespace sl7 {
 static_assert(offsetof(InstDev, c0) % 16 == 0, "c0 is read with 16-byte loads");
-static_assert(sizeof(Partial) == 48, "partial layout");
+static_assert(sizeof(Partial) == 64, "partial layout");
 }  // namespace sl7
