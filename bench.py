@@ -43,6 +43,27 @@ ISSUED = {"bf16": 2 * (3 * 64 * 64 + 64 * 16), "f16": 2 * (3 * 64 * 64 + 64 * 16
 ISSUED["bf16x3"] = ISSUED["f16x3"] = 3 * ISSUED["bf16"]
 
 
+PROFILE_X3 = os.path.join(ROOT, "profiles", "k_sim_mfma_x3_bf16x3_gbm_N2e24_M32.md")
+
+
+def profiled_traffic(path=PROFILE_X3):
+    """HBM bytes per launch of the headline kernel from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel sources have
+    changed since those counters were taken."""
+    import hashlib
+    try:
+        fields = dict(l.split(": ", 1) for l in open(path).read().splitlines()
+                      if l.startswith(("traffic_bytes_per_launch:", "source_sha256:", "source_files:")))
+        h = hashlib.sha256()
+        for f in fields["source_files"].split():
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != fields["source_sha256"]:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -102,10 +123,13 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-paths", type=int, default=2 ** 14)
+    ap.add_argument("--cpu-paths", type=int, default=2 ** 21)
     ap.add_argument("--profile-run", default=None,
                     help="only run the default workload in this precision (plus a 256 MiB "
                          "calibration copy) for rocprofv3; prints no JSON")
+    ap.add_argument("--grab", type=int, default=None,
+                    help="with --profile-run: 64-path blocks per work-queue grab (default plan "
+                         "otherwise)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -132,8 +156,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log(f"calibration copy: {src.numel() * 4} bytes read and written")
+        plan = None
+        if args.grab is not None:
+            plan = dict(waves_per_block=4, blocks_per_cu=2 if args.profile_run != "f32" else 1,
+                        grab=args.grab)
         for _ in range(args.steps):
-            S.simulate(pr, H, prec=args.profile_run, seed=c["seed"], stats=True)
+            S.simulate(pr, H, prec=args.profile_run, seed=c["seed"], stats=True, plan=plan)
         torch.cuda.synchronize()
         log(f"profile run: {args.steps} launches of {args.profile_run}, N={c['N']}, M={c['M']}")
         return
@@ -236,7 +264,8 @@ def main():
                                "T=2, m=5, MLP 4-64x4-5 ReLU", "N": c["N"], "M": c["M"],
                    "seed": c["seed"], "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["bf16"] / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK["bf16"], "traffic": None},
+                     "unit": "TFLOP/s", "frac": achieved / PEAK["bf16"],
+                     "traffic": profiled_traffic()},
         "precision_compare": {
             p: {"path_steps_per_s": ps / r["wall"], "kernel_ms": r["ev_async"] * 1e3,
                 "frac_of_dtype_peak": FLOPS_PER_PATH_STEP * ps / r["ev_async"] / PEAK[p],

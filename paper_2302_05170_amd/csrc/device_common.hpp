@@ -85,8 +85,9 @@ __device__ __forceinline__ void normals4_f64(u32x4 r, double x[4]) {
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Reduces one 64-path block held one path per lane (lane l = path l of the
-// block) in a fixed butterfly order and writes its partial from lane 0.
-// Invalid lanes must pass zeros.
+// block) in a fixed butterfly order (every lane ends with the same sums) and
+// writes its partial with one store from lanes 0..2, 16 bytes each, so the
+// record leaves as one contiguous write.  Invalid lanes must pass zeros.
 __device__ __forceinline__ void block_partial(double f0, double f1, long long clamped,
                                               long long ood, Partial* out) {
   double s0 = f0, s1 = f1, q0 = f0 * f0, q1 = f1 * f1;
@@ -99,11 +100,13 @@ __device__ __forceinline__ void block_partial(double f0, double f1, long long cl
     clamped += __shfl_xor(clamped, off);
     ood += __shfl_xor(ood, off);
   }
-  if ((threadIdx.x & 63) == 0) {
-    Partial p;
-    p.s[0] = s0; p.s[1] = s1; p.q[0] = q0; p.q[1] = q1;
-    p.clamped = clamped; p.ood = ood;
-    *out = p;
+  const int lane = threadIdx.x & 63;
+  if (lane < 3) {
+    // lane 0: s, lane 1: q, lane 2: the two counts
+    const double a = lane == 0 ? s0 : lane == 1 ? q0 : __builtin_bit_cast(double, clamped);
+    const double b = lane == 0 ? s1 : lane == 1 ? q1 : __builtin_bit_cast(double, ood);
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    reinterpret_cast<d2*>(out)[lane] = (d2){a, b};
   }
 }
 

@@ -37,9 +37,37 @@ __device__ __forceinline__ float softplus_f(float z) {
   return relu_bits(z) + __builtin_amdgcn_logf(1.f + u) * 0.693147180559945309f;
 }
 
+// Softplus for the FP32 kernels.  The hardware base-2 logarithm near 1 has
+// an absolute error that does not shrink with its result, and that error,
+// summed over a layer's units and the M steps, is visible at FP32 parity.
+// Here log1p(u), u = e^{-|z|} in (0, 1], comes from the series
+// log1p(u) = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...), s = u / (2 + u) <= 1/3,
+// cut after s^15 (truncation below 1e-9): a few ulps, unbiased.
+__device__ __forceinline__ float softplus_acc(float z) {
+  // u = e^{-|z|} = 2^n e^r, r = -|z| - n ln2 (two-part ln2), |r| <= ln2 / 2
+  const float x = -fabsf(z);
+  const float n = __builtin_rintf(x * 1.44269504088896341f);
+  float r = fmaf(n, -0.693145751953125f, x);
+  r = fmaf(n, -1.428606765330187e-06f, r);
+  const float u = __builtin_ldexpf(__builtin_amdgcn_exp2f(r * 1.44269504088896341f), (int)n);
+  const float s = u * __builtin_amdgcn_rcpf(2.f + u);
+  const float s2 = s * s;
+  float p = 2.f / 15.f;
+  p = fmaf(p, s2, 2.f / 13.f);
+  p = fmaf(p, s2, 2.f / 11.f);
+  p = fmaf(p, s2, 2.f / 9.f);
+  p = fmaf(p, s2, 2.f / 7.f);
+  p = fmaf(p, s2, 2.f / 5.f);
+  p = fmaf(p, s2, 2.f / 3.f);
+  p = fmaf(p, s2, 2.f);
+  return relu_bits(z) + p * s;
+}
+
+// The FP32 kernels' activation (the 16-bit kernels use softplus_f, whose
+// error is far below their operand rounding).
 template <int ACT>
 __device__ __forceinline__ float act_f(float z) {
-  if constexpr (ACT == SL7_RELU) return relu_bits(z); else return softplus_f(z);
+  if constexpr (ACT == SL7_RELU) return relu_bits(z); else return softplus_acc(z);
 }
 
 // ------------------------------------------------------------------------
@@ -208,10 +236,13 @@ __device__ __forceinline__ void split8(f32x4 a, f32x4 b, typename Split16<P>::v8
     if constexpr (P == SL7_BF16X3) {
       const uint32_t u0 = __builtin_bit_cast(uint32_t, v[2 * q]);
       const uint32_t u1 = __builtin_bit_cast(uint32_t, v[2 * q + 1]);
-      const float l0 = v[2 * q] - __builtin_bit_cast(float, u0 & 0xffff0000u);
-      const float l1 = v[2 * q + 1] - __builtin_bit_cast(float, u1 & 0xffff0000u);
       // upper halves of u0 (low result half) and u1 (high result half)
       const uint32_t h = __builtin_amdgcn_perm(u1, u0, 0x07060302u);
+      // x - hi, exact in FP32 (hi is x with its low 16 bits cleared).  A
+      // BF16 dot product against (-1, 0) does the same in one instruction
+      // per value but issues at a lower rate: measured slower here.
+      const float l0 = v[2 * q] - __builtin_bit_cast(float, u0 & 0xffff0000u);
+      const float l1 = v[2 * q + 1] - __builtin_bit_cast(float, u1 & 0xffff0000u);
       const v2 l = __builtin_convertvector((f32x2){l0, l1}, v2);
       const s16x2 hs = __builtin_elementwise_max(__builtin_bit_cast(s16x2, h), (s16x2){0, 0});
       const s16x2 ls = __builtin_elementwise_max(__builtin_bit_cast(s16x2, l), (s16x2){0, 0});
@@ -221,7 +252,8 @@ __device__ __forceinline__ void split8(f32x4 a, f32x4 b, typename Split16<P>::v8
       const float x0 = relu_bits(v[2 * q]), x1 = relu_bits(v[2 * q + 1]);
       const v2 h = __builtin_convertvector((f32x2){x0, x1}, v2);
       const f32x2 back = __builtin_convertvector(h, f32x2);
-      const v2 l = __builtin_convertvector((f32x2){x0 - back[0], x1 - back[1]}, v2);
+      const float l0 = x0 - back[0], l1 = x1 - back[1];
+      const v2 l = __builtin_convertvector((f32x2){l0, l1}, v2);
       wh[q] = __builtin_bit_cast(uint32_t, h);
       wl[q] = __builtin_bit_cast(uint32_t, l);
     }

@@ -98,4 +98,7 @@ hipError_t launch_eval_lane(const double* net, const double* w0full, int d_in, i
 namespace sl7 {
 static_assert(offsetof(InstDev, c0) % 16 == 0, "c0 is read with 16-byte loads");
 static_assert(sizeof(Partial) == 64, "partial layout");
+static_assert(offsetof(Partial, s) == 0 && offsetof(Partial, q) == 16 &&
+                  offsetof(Partial, clamped) == 32 && offsetof(Partial, ood) == 40,
+              "block_partial stores s, q and the counts as three 16-byte pieces");
 }  // namespace sl7
