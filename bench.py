@@ -202,7 +202,7 @@ def main():
                      K=d["theta"][1], instance=d["instance"]) for d in W.cir_instances(256)]
     ps4 = sum(p.N * p.M for p in prs)
     batched = {}
-    for prec in ("bf16x3", "bf16", "f32"):
+    for prec in ("bf16x3", "bf16", "f32", "pwl32"):
         S.simulate_batched(prs, Hc, prec=prec, seed=11, use_graph=True)
         reps = 5 if prec != "f32" else 2
         t0 = time.perf_counter()
@@ -211,6 +211,23 @@ def main():
         dt = (time.perf_counter() - t0) / reps
         batched[prec] = {"path_steps_per_s": ps4 / dt, "ms_per_launch": dt * 1e3}
         log(f"batched {prec}: {ps4 / dt:.3e} path-steps/s ({dt * 1e3:.2f} ms per replay)")
+
+    # the network in its exact piecewise-linear form along Y (ReLU networks):
+    # no GEMMs in the loop; FP32 and FP64 lane arithmetic
+    pwl = {}
+    for prec in ("pwl32", "pwl64"):
+        t0 = time.perf_counter()
+        S.simulate(pr, S.Mlp.load(WEIGHTS), prec=prec, seed=c["seed"], stats=True)
+        torch.cuda.synchronize()
+        first = time.perf_counter() - t0
+        wall_p, ev_p, st_p = time_calls(S, pr, H, prec, c["seed"], args.steps, args.warmup, stats=True)
+        emax_p, e99_p, ns_p = sampled_error(S, pr, H, Ho, prec, c["seed"])
+        pwl[prec] = {"path_steps_per_s": ps / wall_p, "ms_per_run": wall_p * 1e3,
+                     "first_call_ms_incl_compile": first * 1e3,
+                     "max_rel_err_vs_fp64_oracle": emax_p, "p99_rel_err": e99_p,
+                     "sampled_paths": ns_p, "mean_YT": st_p["mean"][0]}
+        log(f"{prec}: {ps / wall_p:.3e} path-steps/s ({wall_p * 1e3:.2f} ms; first call "
+            f"{first * 1e3:.1f} ms incl. compile), max rel err {emax_p:.2e}")
 
     # the paper's OU experiment (eq. 6.5, 4x50 Softplus network) at the path
     # counts of Table 6.1
@@ -278,6 +295,7 @@ def main():
         "c1_f32_path_steps_per_s": c1["N"] * c1["M"] / wall1,
         "adjoint_c3": adj,
         "batched_c4": dict(batched, instances=len(prs), path_steps=ps4),
+        "piecewise_linear_c2": pwl,
         "ou_table61_shape": dict(ou, workload=f"OU theta={W.OU_PAPER['theta']}, Y0={W.OU_PAPER['Y0']}, "
                                               f"T={W.OU_PAPER['T']}, M={W.OU_PAPER['M']}, m=5, "
                                               "MLP 5-50x4-5 Softplus") if ou else None,

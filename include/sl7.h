@@ -63,17 +63,30 @@ extern "C" {
  * on FP32 MFMA.  BF16 / F16: hidden-layer and head GEMM operands rounded
  * (RNE) once to bfloat16 / half, one MFMA pass with FP32 accumulation.
  * BF16X3 / F16X3: the same MFMA instructions on split operands
- * x = hi + lo (hi = rn16(x), lo = rn16(x - hi)) for weights and
+ * x = hi + lo (hi = x rounded to 16 bits -- to nearest, except BF16
+ * activations, which are truncated -- and lo = rn16(x - hi)) for weights and
  * activations, three passes hi*hi + hi*lo + lo*hi accumulated in FP32
  * (close to FP32 accuracy; the one-pass forms carry a rounding bias per
  * step).  In every mode the first layer, the interpolation and the state
- * update stay FP32 and the path mean is reduced in FP64. */
+ * update stay FP32 and the path mean is reduced in FP64.
+ *
+ * PWL32 / PWL64 (ReLU networks only): no GEMMs in the loop.  For a fixed
+ * instance the network's only varying input is Y, and a ReLU network is then
+ * an exactly piecewise-linear function of Y (each unit is affine on either
+ * side of one breakpoint, layer after layer).  The library compiles that
+ * function per instance on the host in FP64 (at most 65536 pieces, else
+ * SL7_EUNSUPPORTED) and each path evaluates y_j = c_j + a_j (Y - o) on its
+ * piece, found through a uniform grid over the breakpoints; lane arithmetic
+ * (piece search, y_j, interpolation, update) in FP32 or FP64.  Mathematically
+ * identical to evaluating the network, to rounding. */
 #define SL7_F64 0
 #define SL7_F32 1
 #define SL7_BF16 2
 #define SL7_F16 3
 #define SL7_BF16X3 4
 #define SL7_F16X3 5
+#define SL7_PWL32 6
+#define SL7_PWL64 7
 
 /* Hidden activations. */
 #define SL7_RELU 0
@@ -167,17 +180,29 @@ int sl7_eval_H(const sl7_mlp* H, int prec, const float* in_dev, int64_t B,
  * collocation map of the model (GBM: y_j = Y exp((mu - sigma^2/2) dt +
  * sigma sqrt(dt) x_j); OU: eq. 6.6 over one step); otherwise H (whose m
  * and d_in = 2 + n_theta must match).  prec: SL7_F64 for either map; F32
- * for either map; BF16, F16, BF16X3 and F16X3 for the network only.
- * YT_dev: NULL, or device buffer of N values (double in F64 mode, float
- * otherwise) that receives Y_T per path.  stats_host: NULL or host struct;
+ * for either map; BF16, F16, BF16X3 and F16X3 for the network only; PWL32
+ * and PWL64 for ReLU networks only (SL7_EUNSUPPORTED otherwise).
+ * YT_dev: NULL, or device buffer of N values (double in F64 and PWL64 modes,
+ * float otherwise) that receives Y_T per path.  stats_host: NULL or host struct;
  * when non-NULL the call synchronises `stream` before returning.
  * plan: NULL for the default/tuned plan. */
 int sl7_simulate(const sl7_problem* pr, const sl7_mlp* H, int prec,
                  uint64_t seed, void* YT_dev, sl7_stats* stats_host,
                  const sl7_plan* plan, void* stream);
 
+/* The piecewise-linear form of a ReLU network H for one instance pr (the
+ * SL7_PWL32 / SL7_PWL64 modes above), computed on the host in FP64.
+ * *n_pieces receives the piece count P.  With brk/anchor/slope/value all
+ * non-NULL (host arrays of P-1, P, P*m and P*m doubles) they receive the
+ * breakpoints (ascending; piece p covers [brk[p-1], brk[p])), the anchors
+ * o_p and, for output j, y_j = value[p*m+j] + slope[p*m+j] (Y - o_p).  Pass
+ * them all NULL to query P.  max_pieces caps P (EUNSUPPORTED beyond it).
+ * No device work. */
+int sl7_pwl_compile(const sl7_mlp* H, const sl7_problem* pr, int max_pieces, int* n_pieces,
+                    double* brk, double* anchor, double* slope, double* value);
+
 /* Many instances of uneven size in one persistent launch (network map,
- * prec F32/BF16/F16).  Work is 64-path blocks ordered longest-M first and
+ * prec F32/BF16/F16/BF16X3/F16X3/PWL32).  Work is 64-path blocks ordered longest-M first and
  * handed out by an atomic work counter; per-instance statistics go to
  * stats_host[n] (synchronises the stream).  The launch sequence is captured
  * once into a hipGraph per distinct (prec, instance table) signature and

@@ -4,6 +4,7 @@ The compute path is libsl7.so (hand-written HIP kernels + C++ host runtime,
 C ABI in include/sl7.h).  This package only marshals arguments: torch
 tensors serve as device buffers and streams.
 """
-from ._lib import (BF16, CIR, F16, F32, F64, GBM, OU, RELU, SOFTPLUS, Sl7Error)  # noqa: F401
+from ._lib import (BF16, CIR, F16, F32, F64, GBM, OU, PWL32, PWL64, RELU, SOFTPLUS,  # noqa: F401
+                   Sl7Error)
 from .api import (Mlp, PRECISIONS, Problem, SL7Adjoint, adjoint, eval_H, gh_nodes,  # noqa: F401
-                  labels, simulate, simulate_batched, train, train_grad)
+                  labels, pwl_compile, simulate, simulate_batched, train, train_grad)

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libsl7.so")
 
 SL7_OK, SL7_EINVAL, SL7_EUNSUPPORTED, SL7_EHIP, SL7_ENOMEM, SL7_ENUMERIC, SL7_EIO = 0, -1, -2, -3, -4, -5, -6
 GBM, OU, CIR = 0, 1, 2
-F64, F32, BF16, F16, BF16X3, F16X3 = 0, 1, 2, 3, 4, 5
+F64, F32, BF16, F16, BF16X3, F16X3, PWL32, PWL64 = 0, 1, 2, 3, 4, 5, 6, 7
 RELU, SOFTPLUS = 0, 1
 MAX_DIN = 8
 
@@ -55,6 +55,7 @@ SIGNATURES = {
     "sl7_mlp_free": (None, [c_p]),
     "sl7_eval_H": (ctypes.c_int, [c_p, ctypes.c_int, c_p, c_i64, c_p, c_p]),
     "sl7_simulate": (ctypes.c_int, [c_p, c_p, ctypes.c_int, c_u64, c_p, c_p, c_p, c_p]),
+    "sl7_pwl_compile": (ctypes.c_int, [c_p, c_p, ctypes.c_int, c_p, c_p, c_p, c_p, c_p]),
     "sl7_simulate_batched": (ctypes.c_int, [c_p, ctypes.c_int, c_p, ctypes.c_int, c_u64, c_p, c_p,
                                             ctypes.c_int, c_p]),
     "sl7_autotune": (ctypes.c_int, [c_p, c_p, ctypes.c_int, ctypes.c_char_p, c_p, c_p]),

@@ -11,7 +11,7 @@ import torch
 from . import _lib as L
 
 PRECISIONS = {"f64": L.F64, "f32": L.F32, "bf16": L.BF16, "f16": L.F16, "bf16x3": L.BF16X3,
-              "f16x3": L.F16X3}
+              "f16x3": L.F16X3, "pwl32": L.PWL32, "pwl64": L.PWL64}
 
 
 def _prec(p) -> int:
@@ -151,7 +151,7 @@ def simulate(pr: Problem, H: Mlp | None = None, prec="f32", seed: int = 42, want
     """Runs sl7_simulate.  Returns (stats dict or None, Y_T tensor or None)."""
     p = _prec(prec)
     if want_yt and yt is None:
-        dt = torch.float64 if p == L.F64 else torch.float32
+        dt = torch.float64 if p in (L.F64, L.PWL64) else torch.float32
         yt = torch.empty(int(pr.N), dtype=dt, device="cuda")
     st = L.Stats()
     pl = _plan(plan)
@@ -161,6 +161,25 @@ def simulate(pr: Problem, H: Mlp | None = None, prec="f32", seed: int = 42, want
                                  ctypes.byref(st) if stats else None,
                                  ctypes.byref(pl) if pl is not None else None, _stream(stream)))
     return (_stats_dict(st) if stats else None), yt
+
+
+def pwl_compile(H: Mlp, pr: Problem, max_pieces: int = 1 << 16) -> dict:
+    """The exact piecewise-linear form of the ReLU network H along Y for
+    instance pr (sl7_pwl_compile, host only): breakpoints [P-1], anchors [P],
+    slopes and values [P, m] with y_j = value + slope (Y - anchor)."""
+    import numpy as np
+    cp = pr.c()
+    n = ctypes.c_int(0)
+    L.check(L.lib().sl7_pwl_compile(H.handle, ctypes.byref(cp), int(max_pieces), ctypes.byref(n),
+                                    None, None, None, None))
+    P, m = n.value, int(pr.m)
+    brk, anc = np.zeros(max(P - 1, 0)), np.zeros(P)
+    slope, value = np.zeros((P, m)), np.zeros((P, m))
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a.size else ctypes.c_void_p(
+        ctypes.addressof(ctypes.c_double()))
+    L.check(L.lib().sl7_pwl_compile(H.handle, ctypes.byref(cp), int(max_pieces), ctypes.byref(n),
+                                    ptr(brk), ptr(anc), ptr(slope), ptr(value)))
+    return {"breaks": brk, "anchor": anc, "slope": slope, "value": value}
 
 
 def simulate_batched(prs: list, H: Mlp, prec="bf16", seed: int = 11, plan: dict | None = None,

@@ -18,6 +18,7 @@
 
 #include "sl7_internal.hpp"
 #include "sl7_host.hpp"
+#include "sl7_pwl.hpp"
 
 namespace sl7 {
 
@@ -215,6 +216,8 @@ void Mlp::drop_device() {
   w0n.reset();
   c0n.reset();
   device = -1;
+  pwl_cache.clear();
+  ++version;
 }
 
 static uint16_t to_bf16_bits(float f) {
@@ -348,6 +351,7 @@ int Mlp::ensure_device(int prec) {
     drop_device();
     device = dev;
   }
+  if (is_pwl(prec)) return SL7_OK;  // tables are built per call (prepare_instances)
   if (prec == SL7_F64) {
     if (net64) return SL7_OK;
     const int m = d.m;
@@ -427,7 +431,9 @@ int check_problem(const sl7_problem* pr, const Mlp* H, int prec, const char* nam
     if (!(pr->theta[2] > 0.0)) return fail(SL7_EINVAL, "%s.theta[2] (gamma) must be > 0", name);
     if (!(pr->Y0 >= 0.0)) return fail(SL7_EINVAL, "%s.Y0 must be >= 0 for CIR", name);
   }
-  if (prec < SL7_F64 || prec > SL7_F16X3) return fail(SL7_EINVAL, "prec=%d unknown", prec);
+  if (prec < SL7_F64 || prec > SL7_PWL64) return fail(SL7_EINVAL, "prec=%d unknown", prec);
+  if (is_pwl(prec) && (!H || H->d.act != SL7_RELU))
+    return fail(SL7_EUNSUPPORTED, "prec=%d (piecewise-linear form) needs a ReLU network", prec);
   if (!H) {
     if (pr->model == SL7_CIR) return fail(SL7_EUNSUPPORTED, "%s: CIR needs a network (no analytic map on the GPU)", name);
     if (prec != SL7_F64 && prec != SL7_F32)
@@ -525,7 +531,9 @@ int fill_nodes(int m, SimArgs& a, double* x_out) {
 
 int default_plan(int prec, sl7_plan* p) {
   p->waves_per_block = 4;
-  p->blocks_per_cu = is_half(prec) ? 2 : 1;  // register-limited occupancy
+  // register-limited occupancy of the MFMA kernels; the lane kernels of the
+  // piecewise-linear form hide their table loads with more waves
+  p->blocks_per_cu = is_pwl(prec) ? 8 : is_half(prec) ? 2 : 1;
   p->grab = 1;
   p->reserved = 0;
   return SL7_OK;
@@ -557,6 +565,11 @@ int prepare_instances(const sl7_problem* prs, int n, const Mlp* H, int prec, uin
     inst[k].yt_offset = yt;
     parts += (prs[k].N + 63) / 64;
     yt += prs[k].N;
+  }
+  if (is_pwl(prec)) {
+    rc = build_pwl_tables(prs, n, const_cast<Mlp*>(H), prec == SL7_PWL64, inst, stream, ws);
+    if (rc) return rc;
+    a.wpack = ws.pwl.p;
   }
   std::vector<int32_t> order(n);
   std::iota(order.begin(), order.end(), 0);
@@ -597,8 +610,13 @@ int launch_instances(const SimArgs& a_in, int n, int64_t N0, const Mlp* H, int p
   SimArgs a = a_in;
   a.grab = plan.grab;
   hipError_t e;
-  const bool mfma = H && prec != SL7_F64;
-  if (mfma) {
+  const bool mfma = H && prec != SL7_F64 && !is_pwl(prec);
+  if (is_pwl(prec)) {
+    e = launch_zero_u64(a.counter, 1, stream);
+    if (e != hipSuccess) return hip_fail(e, "zero counter");
+    e = launch_sim_pwl(prec, a, plan.blocks_per_cu * ws.n_cu, plan.waves_per_block, stream);
+    if (e != hipSuccess) return hip_fail(e, "launch piecewise-linear kernel");
+  } else if (mfma) {
     a.wpack = H->pack[prec]->p;
     e = launch_zero_u64(a.counter, 1, stream);
     if (e != hipSuccess) return hip_fail(e, "zero counter");
@@ -723,6 +741,7 @@ int sl7_mlp_set_params(sl7_mlp* H, const float* params) {
 int sl7_eval_H(const sl7_mlp* Hc, int prec, const float* in_dev, int64_t B, float* out_dev,
                void* stream) {
   if (!Hc) return fail(SL7_EINVAL, "H is NULL");
+  if (is_pwl(prec)) return fail(SL7_EUNSUPPORTED, "eval_H: the piecewise-linear form is per instance (sl7_pwl_compile)");
   if (prec < SL7_F64 || prec > SL7_F16X3) return fail(SL7_EINVAL, "prec=%d unknown", prec);
   if (B < 0) return fail(SL7_EINVAL, "B=%lld must be >= 0", (long long)B);
   if (B > 0 && (!in_dev || !out_dev)) return fail(SL7_EINVAL, "in_dev and out_dev must be non-NULL");

@@ -63,7 +63,8 @@ int check_batch(const sl7_problem* prs, int n, const Mlp* H, int prec) {
   if (!prs) return fail(SL7_EINVAL, "prs is NULL");
   if (n < 1 || n > 65536) return fail(SL7_EINVAL, "n=%d outside [1, 65536]", n);
   if (!H) return fail(SL7_EUNSUPPORTED, "batched launches need a network");
-  if (prec == SL7_F64) return fail(SL7_EUNSUPPORTED, "batched launches run in F32, BF16 or F16");
+  if (prec == SL7_F64)
+    return fail(SL7_EUNSUPPORTED, "batched launches run in F32, BF16, F16, BF16X3, F16X3, PWL32 or PWL64");
   char name[32];
   for (int k = 0; k < n; ++k) {
     snprintf(name, sizeof(name), "prs[%d]", k);
@@ -108,9 +109,17 @@ extern "C" int sl7_simulate_batched(const sl7_problem* prs, int n, const sl7_mlp
   key = fnv1a(&seed, sizeof(seed), key);
   key = fnv1a(&prec, sizeof(prec), key);
   key = fnv1a(&dev, sizeof(dev), key);
-  const void* wp = H->pack[prec]->p;
-  key = fnv1a(&wp, sizeof(wp), key);
-  key = fnv1a(&H->pack[prec]->generation, sizeof(uint64_t), key);
+  if (is_pwl(prec)) {
+    // the tables are built into the entry's own workspace from the weights
+    // of this version of H
+    const void* hp = H;
+    key = fnv1a(&hp, sizeof(hp), key);
+    key = fnv1a(&H->version, sizeof(uint64_t), key);
+  } else {
+    const void* wp = H->pack[prec]->p;
+    key = fnv1a(&wp, sizeof(wp), key);
+    key = fnv1a(&H->pack[prec]->generation, sizeof(uint64_t), key);
+  }
   GraphCache& gc = graph_cache();
   std::lock_guard<std::mutex> lk(gc.mu);
   auto it = gc.entries.find(key);

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
+#include "work_queue.hpp"
 
 namespace sl7 {
 
@@ -439,29 +440,6 @@ __device__ __forceinline__ void lane_rows(const SimArgs& a, int m, int g, float 
         lr[r] = a.ls[j];
       }
   }
-}
-
-__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// Next work item range [item, end) for this wave, or item >= n_items.
-__device__ __forceinline__ uint64_t grab_items(const SimArgs& a, int lane) {
-  unsigned long long it = 0;
-  if (lane == 0) it = atomicAdd(a.counter, (unsigned long long)a.grab);
-  return uniform_u64(__shfl(it, 0));
-}
-
-__device__ __forceinline__ const InstDev* locate(const SimArgs& a, uint64_t item, int64_t& blk) {
-  int lo = 0, hi = a.n_order;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if ((uint64_t)a.item_prefix[mid] <= item) lo = mid; else hi = mid;
-  }
-  blk = (int64_t)item - a.item_prefix[lo];
-  return a.inst + a.order[lo];
 }
 
 // One 64-path block: four groups of 16 paths, each for all M steps.  Lane

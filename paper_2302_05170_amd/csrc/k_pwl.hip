@@ -1,0 +1,178 @@
+// Seven-League step with the collocation network in its exact
+// piecewise-linear form (SL7_PWL32 / SL7_PWL64).
+//
+// For a fixed instance the network's only varying input is Y, and a ReLU
+// network is then a continuous piecewise-linear function of Y; the host
+// compiles it per instance (pwl.cpp).  Here each lane carries one path for
+// all M steps (Algorithm I, steps 3-6):
+//   piece    p = number of breakpoints <= Y, from a uniform grid over the
+//            breakpoints (one cell load) and a short scan either way
+//   H        y_j = c_j + a_j (Y - o)              (m FMAs, the piece's record)
+//   g_m(X)   barycentric interpolation, second form, exact-node branch
+// and the same Philox normals, clamping, domain counting and fixed-order
+// 64-path block sums as the other simulation kernels.  Work is 64-path
+// blocks of all instances from the shared work queue.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "work_queue.hpp"
+
+namespace sl7 {
+
+template <typename T>
+__device__ __forceinline__ int pwl_piece(const char* __restrict__ base, const InstDev& I, T Y) {
+  constexpr bool F64 = sizeof(T) == 8;
+  const int P = I.pwl_P;
+  if (P < 2) return 0;
+  const T* __restrict__ brk = (const T*)(base + I.pwl_brk);
+  const int32_t* __restrict__ grid = (const int32_t*)(base + I.pwl_grid);
+  const T g0 = F64 ? (T)I.pwl_g0 : (T)I.pwl_g0_f;
+  const T ih = F64 ? (T)I.pwl_ih : (T)I.pwl_ih_f;
+  T v = (Y - g0) * ih;
+  v = v > T(0) ? v : T(0);  // also maps NaN to cell 0
+  const T top = (T)(I.pwl_G - 1);
+  v = v < top ? v : top;
+  int p = grid[(int)v];
+  // the cell start is exact for the cell's left edge; rounding of Y - g0 can
+  // put Y one cell off, so scan in both directions
+  while (p < P - 1 && brk[p] <= Y) ++p;
+  while (p > 0 && brk[p - 1] > Y) --p;
+  return p;
+}
+
+template <typename T>
+__device__ __forceinline__ T interp_lane(const T* xs, const T* ls, int m, const T* y, T X) {
+  if constexpr (sizeof(T) == 8) {
+    T num = 0.0, den = 0.0, yh = 0.0;
+    bool hit = false;
+#pragma unroll
+    for (int j = 0; j < kMaxM; ++j) {
+      if (j < m) {
+        if (X == xs[j]) { hit = true; yh = y[j]; }
+        const T t = ls[j] / (X - xs[j]);
+        num = fma(t, y[j], num);
+        den += t;
+      }
+    }
+    return hit ? yh : num / den;
+  } else {
+    // At a node X - x_j == 0 becomes 1e-30: that weight then exceeds the
+    // others by ~28 orders of magnitude and the quotient is y_j to FP32
+    // rounding, without a branch.
+    float num = 0.f, den = 0.f;
+#pragma unroll
+    for (int j = 0; j < kMaxM; ++j) {
+      if (j < m) {
+        float d = X - xs[j];
+        d = d == 0.f ? 1e-30f : d;
+        const float t = ls[j] * fast_rcp(d);
+        num = fmaf(t, y[j], num);
+        den += t;
+      }
+    }
+    return num * fast_rcp(den);
+  }
+}
+
+// Slopes and anchor values of a piece record with 16-byte loads (the record
+// is 16-byte aligned; entries beyond m are never used).
+template <typename T>
+__device__ __forceinline__ void load_record(const T* __restrict__ rec, int m, T* sl, T* va) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  constexpr int per = 16 / (int)sizeof(T);  // entries per 16-byte load
+#pragma unroll
+  for (int q = 0; q < kMaxM / per; ++q) {
+    if (q * per < m) {
+      if constexpr (sizeof(T) == 4) {
+        const f4 a = reinterpret_cast<const f4*>(rec)[q];
+        const f4 c = reinterpret_cast<const f4*>(rec + kMaxM)[q];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) { sl[4 * q + e] = a[e]; va[4 * q + e] = c[e]; }
+      } else {
+        const d2 a = reinterpret_cast<const d2*>(rec)[q];
+        const d2 c = reinterpret_cast<const d2*>(rec + kMaxM)[q];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) { sl[2 * q + e] = a[e]; va[2 * q + e] = c[e]; }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < per; ++e) { sl[per * q + e] = T(0); va[per * q + e] = T(0); }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void pwl_block(const SimArgs& a, const InstDev& I, int64_t blk,
+                                          const T* xs, const T* ls, int lane) {
+  constexpr bool F64 = sizeof(T) == 8;
+  const char* __restrict__ base = (const char*)a.wpack;
+  const T* __restrict__ rec0 = (const T*)(base + I.pwl_rec);
+  const int64_t p = blk * kBlockPaths + lane;
+  const bool valid = p < I.N;
+  const int64_t gp = I.path_offset + p;
+  const uint32_t tag = (uint32_t)I.tag;
+  const int M = I.M, m = a.m;
+  const T dlo = F64 ? (T)I.dom_lo : (T)I.dom_lo_f;
+  const T dhi = F64 ? (T)I.dom_hi : (T)I.dom_hi_f;
+  T Y = F64 ? (T)I.Y0 : (T)I.Y0_f;
+  long long clamped = 0, ood = 0;
+  for (int i0 = 0; i0 < M; i0 += 4) {
+    const u32x4 r = philox_step_quad(a.seed, (uint32_t)(i0 >> 2), gp, tag);
+    T xq[4];
+    if constexpr (F64) normals4_f64(r, xq); else normals4_f32(r, xq);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (i0 + u < M) {
+        if (Y < dlo || Y > dhi) ++ood;
+        const T* __restrict__ rec = rec0 + (int64_t)pwl_piece<T>(base, I, Y) * kPwlStride;
+        T sl[kMaxM], va[kMaxM];
+        load_record<T>(rec, m, sl, va);
+        const T dY = Y - rec[2 * kMaxM];
+        T y[kMaxM];
+#pragma unroll
+        for (int j = 0; j < kMaxM; ++j) y[j] = j < m ? fma(sl[j], dY, va[j]) : T(0);
+        Y = interp_lane<T>(xs, ls, m, y, xq[u]);
+        if (I.clamp_zero && Y < T(0)) { Y = T(0); ++clamped; }
+      }
+    }
+  }
+  if (a.YT && valid) ((T*)a.YT)[I.yt_offset + p] = Y;
+  const double f0 = valid ? (double)Y : 0.0;
+  const double f1 = valid ? fmax((double)Y - I.K, 0.0) : 0.0;
+  block_partial(f0, f1, valid ? clamped : 0, valid ? ood : 0, a.partials + I.part_offset + blk);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sim_pwl(SimArgs a) {
+  constexpr bool F64 = sizeof(T) == 8;
+  const int lane = threadIdx.x & 63;
+  T xs[kMaxM], ls[kMaxM];
+#pragma unroll
+  for (int j = 0; j < kMaxM; ++j) {
+    xs[j] = F64 ? (T)a.xd[j] : (T)a.xs[j];
+    ls[j] = F64 ? (T)a.ld[j] : (T)a.ls[j];
+  }
+  for (;;) {
+    const uint64_t item0 = grab_items(a, lane);
+    if (item0 >= (uint64_t)a.n_items) break;
+    const uint64_t end = min(item0 + (uint64_t)a.grab, (uint64_t)a.n_items);
+    for (uint64_t item = item0; item < end; ++item) {
+      int64_t blk;
+      const InstDev* I = locate(a, item, blk);
+      pwl_block<T>(a, *I, blk, xs, ls, lane);
+    }
+  }
+}
+
+hipError_t launch_sim_pwl(int prec, const SimArgs& a, int grid, int waves_per_block,
+                          hipStream_t s) {
+  const dim3 g((unsigned)grid), b((unsigned)(64 * waves_per_block));
+  if (prec == SL7_PWL64)
+    hipLaunchKernelGGL(k_sim_pwl<double>, g, b, 0, s, a);
+  else
+    hipLaunchKernelGGL(k_sim_pwl<float>, g, b, 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace sl7

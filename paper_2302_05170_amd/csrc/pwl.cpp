@@ -1,0 +1,323 @@
+// Exact piecewise-linear form of a ReLU collocation network along Y.
+//
+// Within one instance dt and theta are fixed, so the network's input is an
+// affine function of the state Y alone (the network maps (Y, dt, theta) to
+// the collocation points, eq. 6.4).  Every ReLU unit is then affine in Y on
+// each side of one breakpoint, every layer maps affine pieces to affine
+// pieces, and the whole map Y -> (y_0..y_{m-1}) is continuous and piecewise
+// linear with finitely many pieces.  The compilation below follows the pieces
+// layer by layer in FP64: on a piece [lo, hi) the layer input is A Y + B;
+// z = W (A Y + B) + b has unit k crossing zero at t_k = -zB_k / zA_k; the
+// crossings inside (lo, hi) split the piece, and on each sub-piece a unit is
+// either on (keeps its affine form) or off (zero).  The head then gives
+// y_j = a_j Y + c'_j on every final piece.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "sl7_host.hpp"
+#include "sl7_pwl.hpp"
+
+namespace sl7 {
+
+namespace {
+
+// One layer's weights in FP64, transposed (WT[k * n_out + o]) so that the
+// products with a piece's sparse input run over contiguous rows.
+struct Dense {
+  int n_in = 0, n_out = 0;
+  std::vector<double> WT, b;
+};
+
+// Pieces of one layer's input: [lo[p], hi[p]) with input A[p] Y + B[p]
+// (rows of n doubles).
+struct Pieces {
+  int n = 0;
+  std::vector<double> lo, hi, A, B;
+  int count() const { return (int)lo.size(); }
+};
+
+}  // namespace
+
+int compile_pwl(const Mlp& H, const sl7_problem& pr, int max_pieces, PwlPieces& out) {
+  const sl7_mlp_desc& d = H.d;
+  if (d.act != SL7_RELU) return fail(SL7_EUNSUPPORTED, "the piecewise-linear form needs a ReLU network");
+  const int m = d.m;
+  std::vector<Dense> L(d.depth + 1);
+  for (int l = 0; l <= d.depth; ++l) {
+    L[l].n_in = (l == 0) ? d.d_in : d.width;
+    L[l].n_out = (l == d.depth) ? m : d.width;
+    L[l].WT.resize((size_t)L[l].n_in * L[l].n_out);
+    L[l].b.resize(L[l].n_out);
+    for (int o = 0; o < L[l].n_out; ++o) {
+      L[l].b[o] = H.b(l, o);
+      for (int k = 0; k < L[l].n_in; ++k) L[l].WT[(size_t)k * L[l].n_out + o] = H.W(l, o, k);
+    }
+  }
+  const double dt = pr.T / pr.M;
+  double in[SL7_MAX_DIN] = {0.0, dt};
+  for (int k = 0; k < n_theta(pr.model); ++k) in[2 + k] = pr.theta[k];
+  // network input h0 = in_scale * (Y, dt, theta) + in_shift = A0 Y + B0
+  Pieces cur;
+  cur.n = d.d_in;
+  cur.lo.push_back(-INFINITY);
+  cur.hi.push_back(INFINITY);
+  cur.A.assign(d.d_in, 0.0);
+  cur.B.assign(d.d_in, 0.0);
+  cur.A[0] = d.in_scale[0];
+  for (int k = 0; k < d.d_in; ++k) cur.B[k] = (k == 0 ? 0.0 : d.in_scale[k] * in[k]) + d.in_shift[k];
+  std::vector<double> zA, zB, t, edges;
+  for (int l = 0; l <= d.depth; ++l) {
+    const Dense& D = L[l];
+    const bool head = (l == d.depth);
+    Pieces next;
+    next.n = D.n_out;
+    zA.resize(D.n_out);
+    zB.resize(D.n_out);
+    t.resize(D.n_out);
+    for (int p = 0; p < cur.count(); ++p) {
+      const double* A = &cur.A[(size_t)p * cur.n];
+      const double* B = &cur.B[(size_t)p * cur.n];
+      std::fill(zA.begin(), zA.end(), 0.0);
+      std::copy(D.b.begin(), D.b.end(), zB.begin());
+      for (int k = 0; k < D.n_in; ++k) {
+        const double a = A[k], bb = B[k];
+        if (a == 0.0 && bb == 0.0) continue;  // unit off on this piece
+        const double* w = &D.WT[(size_t)k * D.n_out];
+        for (int o = 0; o < D.n_out; ++o) {
+          zA[o] += w[o] * a;
+          zB[o] += w[o] * bb;
+        }
+      }
+      const double lo = cur.lo[p], hi = cur.hi[p];
+      if (head) {
+        next.lo.push_back(lo);
+        next.hi.push_back(hi);
+        next.A.insert(next.A.end(), zA.begin(), zA.end());
+        next.B.insert(next.B.end(), zB.begin(), zB.end());
+        continue;
+      }
+      edges.clear();
+      edges.push_back(lo);
+      for (int o = 0; o < D.n_out; ++o) {
+        t[o] = 0.0;
+        if (zA[o] != 0.0) {
+          t[o] = -zB[o] / zA[o];
+          if (t[o] > lo && t[o] < hi) edges.push_back(t[o]);
+        }
+      }
+      std::sort(edges.begin() + 1, edges.end());
+      edges.erase(std::unique(edges.begin() + 1, edges.end()), edges.end());
+      edges.push_back(hi);
+      for (size_t e = 0; e + 1 < edges.size(); ++e) {
+        const double e0 = edges[e], e1 = edges[e + 1];
+        if (!(e0 < e1)) continue;
+        next.lo.push_back(e0);
+        next.hi.push_back(e1);
+        for (int o = 0; o < D.n_out; ++o) {
+          // on over the whole sub-piece: rising unit whose zero is at or
+          // left of e0, falling unit whose zero is at or right of e1, or a
+          // constant positive unit
+          const bool on = zA[o] > 0.0 ? t[o] <= e0 : zA[o] < 0.0 ? t[o] >= e1 : zB[o] > 0.0;
+          next.A.push_back(on ? zA[o] : 0.0);
+          next.B.push_back(on ? zB[o] : 0.0);
+        }
+        if (next.count() > max_pieces)
+          return fail(SL7_EUNSUPPORTED, "the network has more than %d linear pieces in Y", max_pieces);
+      }
+    }
+    cur = std::move(next);
+  }
+  // cur now holds the head's y = A Y + B per piece; anchor each piece at a
+  // point o of it (its left end, or its right end for the first piece) so
+  // that the evaluation c_j + a_j (Y - o) stays well conditioned
+  const int P = cur.count();
+  out.P = P;
+  out.m = m;
+  out.brk.resize(P > 0 ? P - 1 : 0);
+  out.o.resize(P);
+  out.a.assign((size_t)P * m, 0.0);
+  out.c.assign((size_t)P * m, 0.0);
+  for (int p = 0; p < P; ++p) {
+    if (p + 1 < P) out.brk[p] = cur.hi[p];
+    const double o = std::isfinite(cur.lo[p]) ? cur.lo[p] : (std::isfinite(cur.hi[p]) ? cur.hi[p] : 0.0);
+    out.o[p] = o;
+    for (int j = 0; j < m; ++j) {
+      const double a = cur.A[(size_t)p * m + j], b = cur.B[(size_t)p * m + j];
+      out.a[(size_t)p * m + j] = a;
+      out.c[(size_t)p * m + j] = b + a * o;
+      if (!std::isfinite(a) || !std::isfinite(b + a * o))
+        return fail(SL7_ENUMERIC, "non-finite piece coefficients");
+    }
+  }
+  return SL7_OK;
+}
+
+// Uniform lookup grid: cell g starts at piece start[g] = number of
+// breakpoints <= the cell's left edge, so a lookup is one cell index and a
+// short scan.  The grid spans the breakpoints from rank 2 % to rank 98 %:
+// a few far-out breakpoints (units that switch at |Y| in the hundreds) would
+// otherwise stretch the cells until each held dozens; a Y beyond the span
+// starts from the end cell and scans past at most those 2 %.
+void build_grid(const PwlPieces& pw, int cells, std::vector<int32_t>& start, double& g0,
+                double& inv_h) {
+  start.clear();
+  g0 = 0.0;
+  inv_h = 0.0;
+  if (pw.P < 2) return;
+  const int nb = (int)pw.brk.size();
+  const double lo = pw.brk[(size_t)(0.02 * (nb - 1))];
+  const double hi = pw.brk[(size_t)std::ceil(0.98 * (nb - 1))];
+  const double h = (hi > lo) ? (hi - lo) / cells : 1.0;
+  g0 = lo;
+  inv_h = 1.0 / h;
+  start.resize(cells);
+  size_t k = 0;
+  for (int g = 0; g < cells; ++g) {
+    const double e = lo + g * h;
+    while (k < pw.brk.size() && pw.brk[k] <= e) ++k;
+    start[g] = (int32_t)k;
+  }
+}
+
+// The form depends on the instance only through the model, dt and theta.
+static std::array<double, 5> pwl_key(const sl7_problem& pr) {
+  return {(double)pr.model, pr.T / pr.M, pr.theta[0], pr.theta[1], pr.theta[2]};
+}
+
+namespace {
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+template <typename T>
+void put(std::vector<char>& buf, size_t off, const T& v) {
+  std::memcpy(buf.data() + off, &v, sizeof(T));
+}
+
+}  // namespace
+
+// Compiled forms of n instances: cached ones from H's cache, the others
+// compiled on host threads (instances are independent) and then cached.
+static int pwl_lookup_all(const sl7_problem* prs, int n, Mlp* H,
+                          std::vector<std::shared_ptr<PwlPieces>>& pw) {
+  pw.assign(n, nullptr);
+  std::vector<int> todo;
+  {
+    std::lock_guard<std::mutex> lk(H->mu);
+    for (int k = 0; k < n; ++k) {
+      auto it = H->pwl_cache.find(pwl_key(prs[k]));
+      if (it != H->pwl_cache.end()) pw[k] = it->second; else todo.push_back(k);
+    }
+  }
+  if (todo.empty()) return SL7_OK;
+  std::vector<int> rcs(todo.size(), SL7_OK);
+  std::vector<std::string> errs(todo.size());
+  const int nt = (int)std::min<size_t>(todo.size(), std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+  std::atomic<size_t> next(0);
+  auto work = [&]() {
+    for (size_t i = next++; i < todo.size(); i = next++) {
+      std::shared_ptr<PwlPieces> q(new PwlPieces());
+      rcs[i] = compile_pwl(*H, prs[todo[i]], kPwlMaxPieces, *q);
+      if (rcs[i]) errs[i] = sl7_last_error(); else pw[todo[i]] = q;
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back(work);
+  work();
+  for (auto& x : th) x.join();
+  for (size_t i = 0; i < todo.size(); ++i)
+    if (rcs[i]) return fail(rcs[i], "prs[%d]: %s", todo[i], errs[i].c_str());
+  std::lock_guard<std::mutex> lk(H->mu);
+  if (H->pwl_cache.size() + todo.size() > 4096) H->pwl_cache.clear();
+  for (int k : todo) H->pwl_cache[pwl_key(prs[k])] = pw[k];
+  return SL7_OK;
+}
+
+int build_pwl_tables(const sl7_problem* prs, int n, Mlp* H, bool f64, std::vector<InstDev>& inst,
+                     hipStream_t stream, Workspace& ws) {
+  const size_t el = f64 ? sizeof(double) : sizeof(float);
+  std::vector<std::shared_ptr<PwlPieces>> pw;
+  int rc0 = pwl_lookup_all(prs, n, H, pw);
+  if (rc0) return rc0;
+  std::vector<char> buf;
+  for (int k = 0; k < n; ++k) {
+    const PwlPieces& P = *pw[k];
+    std::vector<int32_t> start;
+    double g0, ih;
+    const int cells = P.P < 2 ? 0 : (int)std::min<int64_t>(
+        65536, std::max<int64_t>(16, (int64_t)1 << (int)std::ceil(std::log2(8.0 * (P.P - 1)))));
+    build_grid(P, cells, start, g0, ih);
+    InstDev& I = inst[k];
+    const size_t rec = align256(buf.size());
+    const size_t brk = align256(rec + (size_t)P.P * kPwlStride * el);
+    const size_t grid = align256(brk + (size_t)std::max(P.P - 1, 0) * el);
+    const size_t end = align256(grid + start.size() * sizeof(int32_t));
+    buf.resize(end, 0);
+    for (int p = 0; p < P.P; ++p) {
+      const size_t r = rec + (size_t)p * kPwlStride * el;
+      for (int j = 0; j < P.m; ++j) {
+        const double a = P.a[(size_t)p * P.m + j], c = P.c[(size_t)p * P.m + j];
+        if (f64) {
+          put(buf, r + j * el, a);
+          put(buf, r + (kMaxM + j) * el, c);
+        } else {
+          put(buf, r + j * el, (float)a);
+          put(buf, r + (kMaxM + j) * el, (float)c);
+        }
+      }
+      if (f64) put(buf, r + 2 * kMaxM * el, P.o[p]); else put(buf, r + 2 * kMaxM * el, (float)P.o[p]);
+    }
+    for (int q = 0; q + 1 < P.P; ++q) {
+      if (f64) put(buf, brk + q * el, P.brk[q]); else put(buf, brk + q * el, (float)P.brk[q]);
+    }
+    if (!start.empty()) std::memcpy(buf.data() + grid, start.data(), start.size() * sizeof(int32_t));
+    I.pwl_rec = (int64_t)rec;
+    I.pwl_brk = (int64_t)brk;
+    I.pwl_grid = (int64_t)grid;
+    I.pwl_P = P.P;
+    I.pwl_G = cells;
+    I.pwl_g0 = g0;
+    I.pwl_ih = ih;
+    I.pwl_g0_f = (float)g0;
+    I.pwl_ih_f = (float)ih;
+  }
+  int rc = ws.pwl.reserve(std::max<size_t>(buf.size(), 256));
+  if (rc) return rc;
+  const hipError_t e = hipMemcpyAsync(ws.pwl.p, buf.data(), buf.size(), hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(piecewise-linear tables)");
+  return SL7_OK;
+}
+
+}  // namespace sl7
+
+extern "C" int sl7_pwl_compile(const sl7_mlp* Hc, const sl7_problem* pr, int max_pieces,
+                               int* n_pieces, double* brk, double* anchor, double* slope,
+                               double* value) {
+  using namespace sl7;
+  Mlp* H = const_cast<Mlp*>(reinterpret_cast<const Mlp*>(Hc));
+  if (!H) return fail(SL7_EINVAL, "H is NULL");
+  if (!n_pieces) return fail(SL7_EINVAL, "n_pieces is NULL");
+  int rc = check_problem(pr, H, SL7_PWL64, "pr");
+  if (rc) return rc;
+  if (max_pieces < 1) return fail(SL7_EINVAL, "max_pieces=%d must be >= 1", max_pieces);
+  const bool all = brk && anchor && slope && value;
+  if (!all && (brk || anchor || slope || value))
+    return fail(SL7_EINVAL, "brk, anchor, slope and value must all be NULL or all non-NULL");
+  PwlPieces pw;
+  {
+    std::lock_guard<std::mutex> lk(H->mu);
+    rc = compile_pwl(*H, *pr, max_pieces, pw);
+  }
+  if (rc) return rc;
+  *n_pieces = pw.P;
+  if (!all) return SL7_OK;
+  std::copy(pw.brk.begin(), pw.brk.end(), brk);
+  std::copy(pw.o.begin(), pw.o.end(), anchor);
+  std::copy(pw.a.begin(), pw.a.end(), slope);
+  std::copy(pw.c.begin(), pw.c.end(), value);
+  return SL7_OK;
+}

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -37,6 +39,7 @@ struct Workspace {
   std::mutex mu;
   int n_cu = 0;
   DevBuf inst, prefix, order, counter, partials, stats, chunks;
+  DevBuf pwl;     // piecewise-linear tables of the instances (PWL modes)
   DevBuf aux[8];  // adjoint checkpoints, trainer buffers, ...
   sl7_stats* stats_host = nullptr;
   int stats_host_n = 0;
@@ -44,6 +47,8 @@ struct Workspace {
 };
 
 Workspace& workspace(int dev);
+
+struct PwlPieces;
 
 // The network handle behind sl7_mlp.
 struct Mlp {
@@ -56,6 +61,10 @@ struct Mlp {
   std::unique_ptr<DevBuf> pack[6];  // MFMA register layouts, by precision
   std::unique_ptr<DevBuf> net64, w0full, w0n, c0n;
   std::unique_ptr<DevBuf> net32, wth64, wth32;  // adjoint lane layouts
+  // compiled piecewise-linear forms by instance (model, dt, theta); cleared
+  // with the device copies whenever the parameters change
+  std::map<std::array<double, 5>, std::shared_ptr<PwlPieces>> pwl_cache;
+  uint64_t version = 0;  // bumped whenever the parameters change
 
   void layout();
   float W(int l, int o, int k) const;

@@ -27,6 +27,14 @@ struct alignas(16) InstDev {
   float K_f, Y0_f, dt_f;
   float dom_lo_f, dom_hi_f;  // float Y is out of domain iff Y < dom_lo_f or Y > dom_hi_f
   int32_t pad_[2];
+  // piecewise-linear form of the network (SL7_PWL32 / SL7_PWL64): byte
+  // offsets, from the table base, of the piece records, the breakpoints and
+  // the lookup grid; piece and grid-cell counts; grid origin and inverse
+  // cell width
+  int64_t pwl_rec, pwl_brk, pwl_grid;
+  int32_t pwl_P, pwl_G;
+  float pwl_g0_f, pwl_ih_f;
+  double pwl_g0, pwl_ih;
   double K, Y0, dt, dom_lo, dom_hi;
   double A[kMaxM], B[kMaxM];  // analytic map: y_j = A_j * Y + B_j
   alignas(16) float c0[kWidth]; // network: first-layer constant (dt, theta folded)
@@ -70,6 +78,13 @@ constexpr int kSlotsF = 48 + 4 + 12 + 1 + 4;  // 69
 constexpr int kSlotsX3 = kSlotsH + 24 + 2;    // 69
 
 inline bool is_x3(int prec) { return prec == SL7_BF16X3 || prec == SL7_F16X3; }
+inline bool is_pwl(int prec) { return prec == SL7_PWL32 || prec == SL7_PWL64; }
+
+// Piece record of the piecewise-linear form, in the lane arithmetic's type:
+// slopes a[kMaxM], values at the anchor c[kMaxM], anchor o, padding (so
+// records stay 16-byte aligned); piece p gives y_j = c_j + a_j (Y - o) for
+// brk[p-1] <= Y < brk[p].
+constexpr int kPwlStride = 20;
 inline bool is_half(int prec) { return prec == SL7_BF16 || prec == SL7_F16 || is_x3(prec); }
 
 // FP64 network layout for the per-lane kernel: wY[64] (first-layer weight of
@@ -78,6 +93,8 @@ inline bool is_half(int prec) { return prec == SL7_BF16 || prec == SL7_F16 || is
 constexpr int kLaneNetDoubles(int m) { return 64 + 3 * (64 * 64 + 64) + 64 * m + m; }
 
 // Launch helpers implemented in the .hip files.
+hipError_t launch_sim_pwl(int prec, const SimArgs& a, int grid, int waves_per_block,
+                          hipStream_t s);
 hipError_t launch_sim_lane(int prec, int use_net, int act, const SimArgs& a,
                            int64_t n_blocks, hipStream_t s);
 hipError_t launch_sim_mfma(int prec, int act, const SimArgs& a, int grid, int waves_per_block,

@@ -1,0 +1,31 @@
+// Piecewise-linear compilation of ReLU collocation networks (host side).
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "sl7_host.hpp"
+
+namespace sl7 {
+
+// The map Y -> (y_0..y_{m-1}) of one instance as P affine pieces in FP64:
+// piece p covers [brk[p-1], brk[p]) (brk[-1] = -inf, brk[P-1] = +inf) and
+// gives y_j = c[p m + j] + a[p m + j] (Y - o[p]).
+struct PwlPieces {
+  int P = 0, m = 0;
+  std::vector<double> brk, o, a, c;
+};
+
+int compile_pwl(const Mlp& H, const sl7_problem& pr, int max_pieces, PwlPieces& out);
+void build_grid(const PwlPieces& pw, int cells, std::vector<int32_t>& start, double& g0,
+                double& inv_h);
+
+// Most pieces a compiled network may have.
+constexpr int kPwlMaxPieces = 1 << 16;
+
+// Compiles (or finds) the tables of n instances, uploads them into ws.pwl in
+// the lane arithmetic's type and fills the instances' table fields.
+int build_pwl_tables(const sl7_problem* prs, int n, Mlp* H, bool f64, std::vector<InstDev>& inst,
+                     hipStream_t stream, Workspace& ws);
+
+}  // namespace sl7
