@@ -186,7 +186,7 @@ def main():
     c3 = W.CONFIGS["c3"]
     pr3 = S.Problem(c3["model"], c3["theta"], c3["Y0"], c3["T"], c3["M"], c3["m"], c3["N"], K=c3["K"])
     adj = {}
-    for prec in ("f64", "f32"):
+    for prec in ("f64", "f32", "pwl64", "pwl32"):
         S.adjoint(pr3, H, prec=prec, seed=c3["seed"], payoff=1, ckpt_every=c3["ckpt"])
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -230,7 +230,11 @@ typedef struct {
 size_t sl7_adjoint_ws_bytes(const sl7_problem* pr, int prec, int ckpt_every);
 
 /* H == NULL: analytic map (GBM, OU).  prec: SL7_F64 or SL7_F32 (the
- * accumulation of the theta-gradients is FP64 in both).  ws_dev: caller's
+ * accumulation of the theta-gradients is FP64 in both); for a ReLU network
+ * also SL7_PWL64 / SL7_PWL32, which back-propagate through the network's
+ * piecewise-linear form: per piece the slope in Y and dy_j/dtheta_k (the
+ * piece's activation pattern held fixed, as back-propagation holds its ReLU
+ * masks) are compiled on the host in FP64 with the pieces.  ws_dev: caller's
  * device workspace of at least sl7_adjoint_ws_bytes.  per_path_dev: NULL or
  * device [N x (2 + n_theta)] doubles receiving (f, df/dY0, df/dtheta...)
  * per path.  ckpt_every in [1, 32].  Synchronises `stream`. */

@@ -20,7 +20,7 @@ struct WsLayout {
 };
 
 WsLayout layout_of(const sl7_problem* pr, int prec, int ckpt) {
-  const size_t el = prec == SL7_F64 ? sizeof(double) : sizeof(float);
+  const size_t el = (prec == SL7_F64 || prec == SL7_PWL64) ? sizeof(double) : sizeof(float);
   const int64_t nseg = (pr->M + ckpt - 1) / ckpt;
   const int64_t nb = (pr->N + 63) / 64;
   WsLayout L;
@@ -116,7 +116,8 @@ extern "C" int sl7_adjoint(const sl7_problem* pr, const sl7_mlp* Hc, int prec, u
   Mlp* H = const_cast<Mlp*>(reinterpret_cast<const Mlp*>(Hc));
   int rc = check_problem(pr, H, prec, "pr");
   if (rc) return rc;
-  if (prec != SL7_F64 && prec != SL7_F32) return fail(SL7_EUNSUPPORTED, "the adjoint runs in F64 or F32");
+  if (prec != SL7_F64 && prec != SL7_F32 && !is_pwl(prec))
+    return fail(SL7_EUNSUPPORTED, "the adjoint runs in F64, F32, PWL64 or PWL32");
   if (payoff != 0 && payoff != 1) return fail(SL7_EINVAL, "payoff=%d must be 0 (Y_T) or 1 (call)", payoff);
   if (ckpt_every < 1 || ckpt_every > 32) return fail(SL7_EINVAL, "ckpt_every=%d outside [1, 32]", ckpt_every);
   if (!out) return fail(SL7_EINVAL, "out is NULL");
@@ -124,7 +125,7 @@ extern "C" int sl7_adjoint(const sl7_problem* pr, const sl7_mlp* Hc, int prec, u
   if (H && H->d.act != SL7_RELU) return fail(SL7_EUNSUPPORTED, "the adjoint back-propagates ReLU networks only");
   const WsLayout Lw = layout_of(pr, prec, ckpt_every);
   if (ws_bytes < Lw.total) return fail(SL7_EINVAL, "ws_bytes=%zu < %zu needed", ws_bytes, Lw.total);
-  if (H) {
+  if (H && !is_pwl(prec)) {
     rc = H->ensure_adjoint(prec);
     if (rc) return rc;
   }
@@ -135,7 +136,7 @@ extern "C" int sl7_adjoint(const sl7_problem* pr, const sl7_mlp* Hc, int prec, u
   std::lock_guard<std::mutex> lk(ws.mu);
   hipStream_t s = (hipStream_t)stream;
   SimArgs sa;
-  rc = prepare_instances(pr, 1, H, prec, seed, nullptr, s, ws, sa);
+  rc = prepare_instances(pr, 1, H, prec, seed, nullptr, s, ws, sa, /*pwl_theta=*/true);
   if (rc) return rc;
   AdjArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -153,7 +154,12 @@ extern "C" int sl7_adjoint(const sl7_problem* pr, const sl7_mlp* Hc, int prec, u
   }
   analytic_derivs(*pr, sa.xd, a);
   const char* instp = (const char*)ws.inst.p;
-  if (H) {
+  int mode = 0;
+  if (H && is_pwl(prec)) {
+    mode = 2;
+    a.net = sa.wpack;  // the piecewise-linear tables with theta derivatives
+  } else if (H) {
+    mode = 1;
     a.net = prec == SL7_F64 ? H->net64->p : H->net32->p;
     a.wtheta = prec == SL7_F64 ? H->wth64->p : H->wth32->p;
     a.c0 = instp + (prec == SL7_F64 ? offsetof(InstDev, c0d) : offsetof(InstDev, c0));
@@ -165,7 +171,7 @@ extern "C" int sl7_adjoint(const sl7_problem* pr, const sl7_mlp* Hc, int prec, u
   a.per_path = per_path_dev;
   a.seed = seed;
   const int64_t nb = (pr->N + 63) / 64;
-  hipError_t e = launch_adjoint(prec, H ? 1 : 0, a, nb, s);
+  hipError_t e = launch_adjoint(prec, mode, a, nb, s);
   if (e != hipSuccess) return hip_fail(e, "launch adjoint");
   double res[12];
   e = hipMemcpyAsync(res, a.result, sizeof(res), hipMemcpyDeviceToHost, s);

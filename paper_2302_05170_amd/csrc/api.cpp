@@ -552,7 +552,8 @@ int check_plan(const sl7_plan* p) {
 // and fills the kernel arguments.  The work order is longest M first (LPT):
 // 64-path blocks of long instances are handed out before short ones.
 int prepare_instances(const sl7_problem* prs, int n, const Mlp* H, int prec, uint64_t seed,
-                      void* YT_dev, hipStream_t stream, Workspace& ws, SimArgs& a) {
+                      void* YT_dev, hipStream_t stream, Workspace& ws, SimArgs& a,
+                      bool pwl_theta) {
   std::memset(&a, 0, sizeof(a));
   double x[SL7_MAX_M];
   int rc = fill_nodes(prs[0].m, a, x);
@@ -567,7 +568,8 @@ int prepare_instances(const sl7_problem* prs, int n, const Mlp* H, int prec, uin
     yt += prs[k].N;
   }
   if (is_pwl(prec)) {
-    rc = build_pwl_tables(prs, n, const_cast<Mlp*>(H), prec == SL7_PWL64, inst, stream, ws);
+    rc = build_pwl_tables(prs, n, const_cast<Mlp*>(H), prec == SL7_PWL64, pwl_theta, inst, stream,
+                          ws);
     if (rc) return rc;
     a.wpack = ws.pwl.p;
   }

@@ -7,14 +7,17 @@
 // is stored), then for each step backwards
 //   ybar_j = lambda * L_j(X)                 (L_j the Lagrange basis at X)
 //   lambda <- sum_j ybar_j dy_j/dY,  thetabar += sum_j ybar_j dy_j/dtheta
-// where dy/d(Y, theta) comes from the analytic map or from back-propagation
-// through the network (eq. 6.3/6.4; ReLU masks kept in registers).  Starts
+// where dy/d(Y, theta) comes from the analytic map, from back-propagation
+// through the network (eq. 6.3/6.4; ReLU masks kept in registers) or, for a
+// ReLU network in its piecewise-linear form, from the piece's record (slope
+// in Y and the theta derivatives compiled on the host).  Starts
 // from lambda = f'(Y_T); a CIR step clamped to 0 passes no gradient.
 // thetabar accumulates in FP64.  One path per lane, one 64-path block per
 // workgroup; block sums in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
+#include "pwl_device.hpp"
 #include "sl7_adjoint.hpp"
 
 namespace sl7 {
@@ -28,13 +31,25 @@ __device__ __forceinline__ T step_normal(const AdjArgs& a, int i, int64_t gp, ui
   return u == 0 ? x[0] : (u == 1 ? x[1] : (u == 2 ? x[2] : x[3]));
 }
 
+// Map evaluation modes of the adjoint.
+constexpr int kAdjAnalytic = 0, kAdjNet = 1, kAdjPwl = 2;
+
 // Collocation points at Y; for the network the ReLU masks of the four hidden
-// layers are returned in mask[l*2 + (unit/32)] bit (unit%32).
-template <typename T, bool NET>
+// layers are returned in mask[l*2 + (unit/32)] bit (unit%32); for the
+// piecewise-linear form mask[0] holds the piece index.
+template <typename T, int MODE>
 __device__ __forceinline__ void colloc(const AdjArgs& a, const InstDev& I, T Y, T* hA, T* hB,
                                        T y[kMaxM], uint32_t mask[8]) {
   const int m = a.m;
-  if constexpr (NET) {
+  if constexpr (MODE == kAdjPwl) {
+    const char* base = (const char*)a.net;
+    const int p = pwl_piece<T>(base, I, Y);
+    mask[0] = (uint32_t)p;
+    const T* rec = (const T*)(base + I.pwl_rec) + (int64_t)p * kPwlAdjStride;
+    const T dY = Y - rec[2 * kMaxM];
+#pragma unroll
+    for (int j = 0; j < kMaxM; ++j) y[j] = j < m ? fma(rec[j], dY, rec[kMaxM + j]) : T(0);
+  } else if constexpr (MODE == kAdjNet) {
     const T* W = (const T*)a.net;
     const T* c0 = (const T*)a.c0;
     for (int q = 0; q < 8; ++q) mask[q] = 0u;
@@ -106,12 +121,28 @@ __device__ __forceinline__ T basis(const AdjArgs& a, T X, const T y[kMaxM], T L[
 
 // Vector-Jacobian product of the collocation map: given ybar, returns
 // dY = ybar . dy/dY and adds ybar . dy/dtheta_k into thb[k].
-template <typename T, bool NET>
+template <typename T, int MODE>
 __device__ __forceinline__ T vjp(const AdjArgs& a, const InstDev& I, T Y, const T ybar[kMaxM],
                                  const uint32_t mask[8], T* dA, T* dB, double thb[4]) {
   const int m = a.m;
   const int nth = a.n_theta;
-  if constexpr (NET) {
+  if constexpr (MODE == kAdjPwl) {
+    const T* rec = (const T*)((const char*)a.net + I.pwl_rec) + (int64_t)mask[0] * kPwlAdjStride;
+    T dY = T(0);
+#pragma unroll
+    for (int j = 0; j < kMaxM; ++j)
+      if (j < m) dY = fma(ybar[j], rec[j], dY);
+    for (int k = 0; k < nth; ++k) {
+      const T* da = rec + kPwlStride + k * kMaxM;
+      const T* db = rec + kPwlStride + (4 + k) * kMaxM;
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < kMaxM; ++j)
+        if (j < m) s += (double)ybar[j] * ((double)da[j] * (double)Y + (double)db[j]);
+      thb[k] += s;
+    }
+    return dY;
+  } else if constexpr (MODE == kAdjNet) {
     const T* W = (const T*)a.net;
     const T* Wh = W + 64 + 3 * (64 * 64 + 64);
     // cotangent of the last hidden layer
@@ -161,14 +192,15 @@ __device__ __forceinline__ T vjp(const AdjArgs& a, const InstDev& I, T Y, const 
   }
 }
 
-template <typename T, bool NET>
+template <typename T, int MODE>
 __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
   extern __shared__ double lds_adj[];
   const InstDev& I = a.inst[0];
   const int lane = threadIdx.x;
+  // network activations (MODE kAdjNet only), then the segment's states
   T* hA = (T*)lds_adj + lane;
   T* hB = hA + 64 * 64;
-  T* ybuf = hB + 64 * 64;  // [ckpt][64]
+  T* ybuf = (MODE == kAdjNet ? hB + 64 * 64 : (T*)lds_adj + lane);  // [ckpt][64]
   const int64_t p = (int64_t)blockIdx.x * 64 + lane;
   const bool valid = p < I.N;
   const int64_t gp = I.path_offset + p;
@@ -183,7 +215,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
   for (int i = 0; i < M; ++i) {
     if (i % k == 0 && valid) ck[(int64_t)(i / k) * I.N + p] = Y;
     const T X = step_normal<T>(a, i, gp, tag);
-    colloc<T, NET>(a, I, Y, hA, hB, y, mask);
+    colloc<T, MODE>(a, I, Y, hA, hB, y, mask);
     Y = basis<T>(a, X, y, L);
     if (clamp && Y < T(0)) Y = T(0);
   }
@@ -199,7 +231,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
       ybuf[(i - i0) * 64] = Yc;
       if (i + 1 < i1) {
         const T X = step_normal<T>(a, i, gp, tag);
-        colloc<T, NET>(a, I, Yc, hA, hB, y, mask);
+        colloc<T, MODE>(a, I, Yc, hA, hB, y, mask);
         Yc = basis<T>(a, X, y, L);
         if (clamp && Yc < T(0)) Yc = T(0);
       }
@@ -207,12 +239,12 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
     for (int i = i1 - 1; i >= i0; --i) {
       const T Yi = ybuf[(i - i0) * 64];
       const T X = step_normal<T>(a, i, gp, tag);
-      colloc<T, NET>(a, I, Yi, hA, hB, y, mask);
+      colloc<T, MODE>(a, I, Yi, hA, hB, y, mask);
       const T g = basis<T>(a, X, y, L);
       const bool pass = !(clamp && g < T(0));
 #pragma unroll
       for (int j = 0; j < kMaxM; ++j) ybar[j] = pass ? lam * L[j] : T(0);
-      lam = vjp<T, NET>(a, I, Yi, ybar, mask, hA, hB, thb);
+      lam = vjp<T, MODE>(a, I, Yi, ybar, mask, hA, hB, thb);
     }
   }
   // per-path outputs: f, dY0, dtheta
@@ -276,28 +308,33 @@ __global__ __launch_bounds__(256) void k_adjoint_finalize(const AdjPartial* __re
   }
 }
 
-size_t adjoint_lds_bytes(int prec, int ckpt) {
-  const size_t el = prec == SL7_F64 ? sizeof(double) : sizeof(float);
-  return el * (2 * 64 * 64 + (size_t)ckpt * 64);
+size_t adjoint_lds_bytes(int prec, int mode, int ckpt) {
+  const size_t el = (prec == SL7_F64 || prec == SL7_PWL64) ? sizeof(double) : sizeof(float);
+  return el * ((mode == kAdjNet ? 2 * 64 * 64 : 0) + (size_t)ckpt * 64);
 }
 
-hipError_t launch_adjoint(int prec, int use_net, const AdjArgs& a, int64_t n_blocks,
-                          hipStream_t s) {
-  const size_t lds = adjoint_lds_bytes(prec, a.ckpt);
-  const void* fn;
-  if (prec == SL7_F64) fn = use_net ? (const void*)k_adjoint<double, true> : (const void*)k_adjoint<double, false>;
-  else fn = use_net ? (const void*)k_adjoint<float, true> : (const void*)k_adjoint<float, false>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+template <typename T, int MODE>
+static hipError_t launch_one(const AdjArgs& a, int64_t n_blocks, size_t lds, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_adjoint<T, MODE>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  dim3 grid((unsigned)n_blocks), block(64);
-  if (prec == SL7_F64) {
-    if (use_net) hipLaunchKernelGGL((k_adjoint<double, true>), grid, block, lds, s, a);
-    else hipLaunchKernelGGL((k_adjoint<double, false>), grid, block, lds, s, a);
+  hipLaunchKernelGGL((k_adjoint<T, MODE>), dim3((unsigned)n_blocks), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(int prec, int mode, const AdjArgs& a, int64_t n_blocks, hipStream_t s) {
+  const size_t lds = adjoint_lds_bytes(prec, mode, a.ckpt);
+  const bool f64 = prec == SL7_F64 || prec == SL7_PWL64;
+  hipError_t e;
+  if (f64) {
+    e = mode == kAdjNet ? launch_one<double, kAdjNet>(a, n_blocks, lds, s)
+        : mode == kAdjPwl ? launch_one<double, kAdjPwl>(a, n_blocks, lds, s)
+                          : launch_one<double, kAdjAnalytic>(a, n_blocks, lds, s);
   } else {
-    if (use_net) hipLaunchKernelGGL((k_adjoint<float, true>), grid, block, lds, s, a);
-    else hipLaunchKernelGGL((k_adjoint<float, false>), grid, block, lds, s, a);
+    e = mode == kAdjNet ? launch_one<float, kAdjNet>(a, n_blocks, lds, s)
+        : mode == kAdjPwl ? launch_one<float, kAdjPwl>(a, n_blocks, lds, s)
+                          : launch_one<float, kAdjAnalytic>(a, n_blocks, lds, s);
   }
-  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_adjoint_finalize, dim3(1), dim3(256), 0, s, a.partials, n_blocks,
                      a.inst_N, a.result);

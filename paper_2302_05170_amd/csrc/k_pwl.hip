@@ -15,30 +15,10 @@
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
+#include "pwl_device.hpp"
 #include "work_queue.hpp"
 
 namespace sl7 {
-
-template <typename T>
-__device__ __forceinline__ int pwl_piece(const char* __restrict__ base, const InstDev& I, T Y) {
-  constexpr bool F64 = sizeof(T) == 8;
-  const int P = I.pwl_P;
-  if (P < 2) return 0;
-  const T* __restrict__ brk = (const T*)(base + I.pwl_brk);
-  const int32_t* __restrict__ grid = (const int32_t*)(base + I.pwl_grid);
-  const T g0 = F64 ? (T)I.pwl_g0 : (T)I.pwl_g0_f;
-  const T ih = F64 ? (T)I.pwl_ih : (T)I.pwl_ih_f;
-  T v = (Y - g0) * ih;
-  v = v > T(0) ? v : T(0);  // also maps NaN to cell 0
-  const T top = (T)(I.pwl_G - 1);
-  v = v < top ? v : top;
-  int p = grid[(int)v];
-  // the cell start is exact for the cell's left edge; rounding of Y - g0 can
-  // put Y one cell off, so scan in both directions
-  while (p < P - 1 && brk[p] <= Y) ++p;
-  while (p > 0 && brk[p - 1] > Y) --p;
-  return p;
-}
 
 template <typename T>
 __device__ __forceinline__ T interp_lane(const T* xs, const T* ls, int m, const T* y, T X) {

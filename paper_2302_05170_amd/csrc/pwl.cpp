@@ -33,20 +33,25 @@ struct Dense {
   std::vector<double> WT, b;
 };
 
-// Pieces of one layer's input: [lo[p], hi[p]) with input A[p] Y + B[p]
-// (rows of n doubles).
+// Pieces of one layer's input: [lo[p], hi[p]) with, per piece, V rows of n
+// doubles: the input's slope A and intercept B in Y (input = A Y + B), then,
+// when theta derivatives are followed, dA/dtheta_k and dB/dtheta_k.
 struct Pieces {
-  int n = 0;
-  std::vector<double> lo, hi, A, B;
+  int n = 0, V = 2;
+  std::vector<double> lo, hi, rows;
   int count() const { return (int)lo.size(); }
+  double* row(int p, int v) { return &rows[((size_t)p * V + v) * n]; }
 };
 
 }  // namespace
 
-int compile_pwl(const Mlp& H, const sl7_problem& pr, int max_pieces, PwlPieces& out) {
+int compile_pwl(const Mlp& H, const sl7_problem& pr, int max_pieces, PwlPieces& out,
+                bool with_theta) {
   const sl7_mlp_desc& d = H.d;
   if (d.act != SL7_RELU) return fail(SL7_EUNSUPPORTED, "the piecewise-linear form needs a ReLU network");
   const int m = d.m;
+  const int nth = with_theta ? n_theta(pr.model) : 0;
+  const int V = 2 + 2 * nth;
   std::vector<Dense> L(d.depth + 1);
   for (int l = 0; l <= d.depth; ++l) {
     L[l].n_in = (l == 0) ? d.d_in : d.width;
@@ -61,44 +66,47 @@ int compile_pwl(const Mlp& H, const sl7_problem& pr, int max_pieces, PwlPieces& 
   const double dt = pr.T / pr.M;
   double in[SL7_MAX_DIN] = {0.0, dt};
   for (int k = 0; k < n_theta(pr.model); ++k) in[2 + k] = pr.theta[k];
-  // network input h0 = in_scale * (Y, dt, theta) + in_shift = A0 Y + B0
+  // network input h0 = in_scale * (Y, dt, theta) + in_shift = A0 Y + B0;
+  // dB0/dtheta_k = in_scale[2 + k] e_{2+k}, dA0/dtheta_k = 0
   Pieces cur;
   cur.n = d.d_in;
+  cur.V = V;
   cur.lo.push_back(-INFINITY);
   cur.hi.push_back(INFINITY);
-  cur.A.assign(d.d_in, 0.0);
-  cur.B.assign(d.d_in, 0.0);
-  cur.A[0] = d.in_scale[0];
-  for (int k = 0; k < d.d_in; ++k) cur.B[k] = (k == 0 ? 0.0 : d.in_scale[k] * in[k]) + d.in_shift[k];
-  std::vector<double> zA, zB, t, edges;
+  cur.rows.assign((size_t)V * d.d_in, 0.0);
+  cur.row(0, 0)[0] = d.in_scale[0];
+  for (int k = 0; k < d.d_in; ++k)
+    cur.row(0, 1)[k] = (k == 0 ? 0.0 : d.in_scale[k] * in[k]) + d.in_shift[k];
+  for (int k = 0; k < nth; ++k) cur.row(0, 2 + nth + k)[2 + k] = d.in_scale[2 + k];
+  std::vector<double> z, t, edges;
   for (int l = 0; l <= d.depth; ++l) {
     const Dense& D = L[l];
     const bool head = (l == d.depth);
     Pieces next;
     next.n = D.n_out;
-    zA.resize(D.n_out);
-    zB.resize(D.n_out);
+    next.V = V;
+    z.resize((size_t)V * D.n_out);
     t.resize(D.n_out);
     for (int p = 0; p < cur.count(); ++p) {
-      const double* A = &cur.A[(size_t)p * cur.n];
-      const double* B = &cur.B[(size_t)p * cur.n];
-      std::fill(zA.begin(), zA.end(), 0.0);
-      std::copy(D.b.begin(), D.b.end(), zB.begin());
-      for (int k = 0; k < D.n_in; ++k) {
-        const double a = A[k], bb = B[k];
-        if (a == 0.0 && bb == 0.0) continue;  // unit off on this piece
-        const double* w = &D.WT[(size_t)k * D.n_out];
-        for (int o = 0; o < D.n_out; ++o) {
-          zA[o] += w[o] * a;
-          zB[o] += w[o] * bb;
+      std::fill(z.begin(), z.end(), 0.0);
+      std::copy(D.b.begin(), D.b.end(), z.begin() + D.n_out);  // the intercept row gets b
+      for (int v = 0; v < V; ++v) {
+        const double* x = cur.row(p, v);
+        double* zv = &z[(size_t)v * D.n_out];
+        for (int k = 0; k < D.n_in; ++k) {
+          const double xk = x[k];
+          if (xk == 0.0) continue;  // unit off on this piece (or no dependence)
+          const double* w = &D.WT[(size_t)k * D.n_out];
+          for (int o = 0; o < D.n_out; ++o) zv[o] += w[o] * xk;
         }
       }
+      const double* zA = &z[0];
+      const double* zB = &z[D.n_out];
       const double lo = cur.lo[p], hi = cur.hi[p];
       if (head) {
         next.lo.push_back(lo);
         next.hi.push_back(hi);
-        next.A.insert(next.A.end(), zA.begin(), zA.end());
-        next.B.insert(next.B.end(), zB.begin(), zB.end());
+        next.rows.insert(next.rows.end(), z.begin(), z.end());
         continue;
       }
       edges.clear();
@@ -118,13 +126,15 @@ int compile_pwl(const Mlp& H, const sl7_problem& pr, int max_pieces, PwlPieces& 
         if (!(e0 < e1)) continue;
         next.lo.push_back(e0);
         next.hi.push_back(e1);
+        const size_t base = next.rows.size();
+        next.rows.resize(base + (size_t)V * D.n_out, 0.0);
         for (int o = 0; o < D.n_out; ++o) {
           // on over the whole sub-piece: rising unit whose zero is at or
           // left of e0, falling unit whose zero is at or right of e1, or a
           // constant positive unit
           const bool on = zA[o] > 0.0 ? t[o] <= e0 : zA[o] < 0.0 ? t[o] >= e1 : zB[o] > 0.0;
-          next.A.push_back(on ? zA[o] : 0.0);
-          next.B.push_back(on ? zB[o] : 0.0);
+          if (on)
+            for (int v = 0; v < V; ++v) next.rows[base + (size_t)v * D.n_out + o] = z[(size_t)v * D.n_out + o];
         }
         if (next.count() > max_pieces)
           return fail(SL7_EUNSUPPORTED, "the network has more than %d linear pieces in Y", max_pieces);
@@ -138,20 +148,27 @@ int compile_pwl(const Mlp& H, const sl7_problem& pr, int max_pieces, PwlPieces& 
   const int P = cur.count();
   out.P = P;
   out.m = m;
+  out.n_theta = nth;
   out.brk.resize(P > 0 ? P - 1 : 0);
   out.o.resize(P);
   out.a.assign((size_t)P * m, 0.0);
   out.c.assign((size_t)P * m, 0.0);
+  out.da.assign((size_t)P * nth * m, 0.0);
+  out.db.assign((size_t)P * nth * m, 0.0);
   for (int p = 0; p < P; ++p) {
     if (p + 1 < P) out.brk[p] = cur.hi[p];
     const double o = std::isfinite(cur.lo[p]) ? cur.lo[p] : (std::isfinite(cur.hi[p]) ? cur.hi[p] : 0.0);
     out.o[p] = o;
     for (int j = 0; j < m; ++j) {
-      const double a = cur.A[(size_t)p * m + j], b = cur.B[(size_t)p * m + j];
+      const double a = cur.row(p, 0)[j], b = cur.row(p, 1)[j];
       out.a[(size_t)p * m + j] = a;
       out.c[(size_t)p * m + j] = b + a * o;
       if (!std::isfinite(a) || !std::isfinite(b + a * o))
         return fail(SL7_ENUMERIC, "non-finite piece coefficients");
+      for (int k = 0; k < nth; ++k) {
+        out.da[((size_t)p * nth + k) * m + j] = cur.row(p, 2 + k)[j];
+        out.db[((size_t)p * nth + k) * m + j] = cur.row(p, 2 + nth + k)[j];
+      }
     }
   }
   return SL7_OK;
@@ -202,7 +219,7 @@ void put(std::vector<char>& buf, size_t off, const T& v) {
 
 // Compiled forms of n instances: cached ones from H's cache, the others
 // compiled on host threads (instances are independent) and then cached.
-static int pwl_lookup_all(const sl7_problem* prs, int n, Mlp* H,
+static int pwl_lookup_all(const sl7_problem* prs, int n, Mlp* H, bool with_theta,
                           std::vector<std::shared_ptr<PwlPieces>>& pw) {
   pw.assign(n, nullptr);
   std::vector<int> todo;
@@ -210,7 +227,12 @@ static int pwl_lookup_all(const sl7_problem* prs, int n, Mlp* H,
     std::lock_guard<std::mutex> lk(H->mu);
     for (int k = 0; k < n; ++k) {
       auto it = H->pwl_cache.find(pwl_key(prs[k]));
-      if (it != H->pwl_cache.end()) pw[k] = it->second; else todo.push_back(k);
+      // a form with theta derivatives serves both uses; one without serves
+      // the simulation only
+      if (it != H->pwl_cache.end() && (!with_theta || it->second->n_theta == n_theta(prs[k].model)))
+        pw[k] = it->second;
+      else
+        todo.push_back(k);
     }
   }
   if (todo.empty()) return SL7_OK;
@@ -221,7 +243,7 @@ static int pwl_lookup_all(const sl7_problem* prs, int n, Mlp* H,
   auto work = [&]() {
     for (size_t i = next++; i < todo.size(); i = next++) {
       std::shared_ptr<PwlPieces> q(new PwlPieces());
-      rcs[i] = compile_pwl(*H, prs[todo[i]], kPwlMaxPieces, *q);
+      rcs[i] = compile_pwl(*H, prs[todo[i]], kPwlMaxPieces, *q, with_theta);
       if (rcs[i]) errs[i] = sl7_last_error(); else pw[todo[i]] = q;
     }
   };
@@ -237,11 +259,12 @@ static int pwl_lookup_all(const sl7_problem* prs, int n, Mlp* H,
   return SL7_OK;
 }
 
-int build_pwl_tables(const sl7_problem* prs, int n, Mlp* H, bool f64, std::vector<InstDev>& inst,
-                     hipStream_t stream, Workspace& ws) {
+int build_pwl_tables(const sl7_problem* prs, int n, Mlp* H, bool f64, bool with_theta,
+                     std::vector<InstDev>& inst, hipStream_t stream, Workspace& ws) {
   const size_t el = f64 ? sizeof(double) : sizeof(float);
+  const int stride = with_theta ? kPwlAdjStride : kPwlStride;
   std::vector<std::shared_ptr<PwlPieces>> pw;
-  int rc0 = pwl_lookup_all(prs, n, H, pw);
+  int rc0 = pwl_lookup_all(prs, n, H, with_theta, pw);
   if (rc0) return rc0;
   std::vector<char> buf;
   for (int k = 0; k < n; ++k) {
@@ -253,12 +276,23 @@ int build_pwl_tables(const sl7_problem* prs, int n, Mlp* H, bool f64, std::vecto
     build_grid(P, cells, start, g0, ih);
     InstDev& I = inst[k];
     const size_t rec = align256(buf.size());
-    const size_t brk = align256(rec + (size_t)P.P * kPwlStride * el);
+    const size_t brk = align256(rec + (size_t)P.P * stride * el);
     const size_t grid = align256(brk + (size_t)std::max(P.P - 1, 0) * el);
     const size_t end = align256(grid + start.size() * sizeof(int32_t));
     buf.resize(end, 0);
     for (int p = 0; p < P.P; ++p) {
-      const size_t r = rec + (size_t)p * kPwlStride * el;
+      const size_t r = rec + (size_t)p * stride * el;
+      if (with_theta) {
+        for (int k = 0; k < P.n_theta; ++k)
+          for (int j = 0; j < P.m; ++j) {
+            const double da = P.da[((size_t)p * P.n_theta + k) * P.m + j];
+            const double db = P.db[((size_t)p * P.n_theta + k) * P.m + j];
+            const size_t oa = r + (kPwlStride + k * kMaxM + j) * el;
+            const size_t ob = r + (kPwlStride + (4 + k) * kMaxM + j) * el;
+            if (f64) { put(buf, oa, da); put(buf, ob, db); }
+            else { put(buf, oa, (float)da); put(buf, ob, (float)db); }
+          }
+      }
       for (int j = 0; j < P.m; ++j) {
         const double a = P.a[(size_t)p * P.m + j], c = P.c[(size_t)p * P.m + j];
         if (f64) {
@@ -310,7 +344,7 @@ extern "C" int sl7_pwl_compile(const sl7_mlp* Hc, const sl7_problem* pr, int max
   PwlPieces pw;
   {
     std::lock_guard<std::mutex> lk(H->mu);
-    rc = compile_pwl(*H, *pr, max_pieces, pw);
+    rc = compile_pwl(*H, *pr, max_pieces, pw, false);
   }
   if (rc) return rc;
   *n_pieces = pw.P;

@@ -13,7 +13,7 @@ struct AdjArgs {
   const InstDev* inst;
   int64_t inst_N;
   int32_t m, n_theta, ckpt, payoff;
-  const void* net;     // lane layout of the network (T), NULL for the analytic map
+  const void* net;     // lane layout of the network (T), the piecewise-linear tables, or NULL
   const void* c0;      // first-layer constant of the instance (T, device)
   const void* wtheta;  // [n_theta x 64] first-layer weight of theta_k times its scale (T)
   void* ckpt_buf;      // [ceil(M/ckpt) x N] states (T)
@@ -26,8 +26,9 @@ struct AdjArgs {
   double dA[4][kMaxM], dB[4][kMaxM];  // analytic map: d(A_j, B_j)/dtheta_k
 };
 
-size_t adjoint_lds_bytes(int prec, int ckpt);
-hipError_t launch_adjoint(int prec, int use_net, const AdjArgs& a, int64_t n_blocks,
-                          hipStream_t s);
+// mode: 0 analytic map, 1 network (lane back-propagation), 2 piecewise-
+// linear form (a.net = table base).  prec F64 / PWL64 run in double.
+size_t adjoint_lds_bytes(int prec, int mode, int ckpt);
+hipError_t launch_adjoint(int prec, int mode, const AdjArgs& a, int64_t n_blocks, hipStream_t s);
 
 }  // namespace sl7

@@ -79,8 +79,11 @@ int check_desc(const sl7_mlp_desc* d);
 int check_problem(const sl7_problem* pr, const Mlp* H, int prec, const char* name);
 int check_plan(const sl7_plan* p);
 int default_plan(int prec, sl7_plan* p);
+// pwl_theta: in the PWL modes, build the adjoint's records (with theta
+// derivatives) instead of the simulation's.
 int prepare_instances(const sl7_problem* prs, int n, const Mlp* H, int prec, uint64_t seed,
-                      void* YT_dev, hipStream_t stream, Workspace& ws, SimArgs& a);
+                      void* YT_dev, hipStream_t stream, Workspace& ws, SimArgs& a,
+                      bool pwl_theta = false);
 int launch_instances(const SimArgs& a, int n, int64_t N0, const Mlp* H, int prec,
                      const sl7_plan& plan, hipStream_t stream, Workspace& ws);
 int run_instances(const sl7_problem* prs, int n, const Mlp* H, int prec, uint64_t seed,

@@ -85,6 +85,9 @@ inline bool is_pwl(int prec) { return prec == SL7_PWL32 || prec == SL7_PWL64; }
 // records stay 16-byte aligned); piece p gives y_j = c_j + a_j (Y - o) for
 // brk[p-1] <= Y < brk[p].
 constexpr int kPwlStride = 20;
+// Adjoint records: the same 20 entries, then da[4][kMaxM] and db[4][kMaxM]
+// with dy_j/dtheta_k = da[k][j] Y + db[k][j] on the piece.
+constexpr int kPwlAdjStride = kPwlStride + 8 * kMaxM;
 inline bool is_half(int prec) { return prec == SL7_BF16 || prec == SL7_F16 || is_x3(prec); }
 
 // FP64 network layout for the per-lane kernel: wY[64] (first-layer weight of

@@ -11,12 +11,17 @@ namespace sl7 {
 // The map Y -> (y_0..y_{m-1}) of one instance as P affine pieces in FP64:
 // piece p covers [brk[p-1], brk[p]) (brk[-1] = -inf, brk[P-1] = +inf) and
 // gives y_j = c[p m + j] + a[p m + j] (Y - o[p]).
+// With theta derivatives (compile_pwl(..., with_theta = true)):
+// dy_j/dtheta_k = da[(p n_theta + k) m + j] Y + db[(p n_theta + k) m + j]
+// on piece p (the pieces' activation pattern held fixed, as back-propagation
+// through the network holds its ReLU masks).
 struct PwlPieces {
-  int P = 0, m = 0;
-  std::vector<double> brk, o, a, c;
+  int P = 0, m = 0, n_theta = 0;
+  std::vector<double> brk, o, a, c, da, db;
 };
 
-int compile_pwl(const Mlp& H, const sl7_problem& pr, int max_pieces, PwlPieces& out);
+int compile_pwl(const Mlp& H, const sl7_problem& pr, int max_pieces, PwlPieces& out,
+                bool with_theta);
 void build_grid(const PwlPieces& pw, int cells, std::vector<int32_t>& start, double& g0,
                 double& inv_h);
 
@@ -25,7 +30,9 @@ constexpr int kPwlMaxPieces = 1 << 16;
 
 // Compiles (or finds) the tables of n instances, uploads them into ws.pwl in
 // the lane arithmetic's type and fills the instances' table fields.
-int build_pwl_tables(const sl7_problem* prs, int n, Mlp* H, bool f64, std::vector<InstDev>& inst,
-                     hipStream_t stream, Workspace& ws);
+// with_theta: records of kPwlAdjStride entries carrying the theta
+// derivatives (the adjoint), else kPwlStride.
+int build_pwl_tables(const sl7_problem* prs, int n, Mlp* H, bool f64, bool with_theta,
+                     std::vector<InstDev>& inst, hipStream_t stream, Workspace& ws);
 
 }  // namespace sl7

@@ -134,3 +134,42 @@ def test_autograd_function(S, H):
     assert abs(v.item() - g["value"]) == 0.0
     assert abs(Y0.grad.item() - 2 * g["grad"][0]) <= 1e-15
     assert np.allclose(th.grad.numpy(), 2 * np.array(g["grad"][1:]), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("payoff", [0, 1])
+def test_piecewise_linear_adjoint_matches_oracle_tangents(S, H, Ho, payoff):
+    """The reverse sweep through the compiled piecewise-linear form (slope in
+    Y and compiled theta derivatives per piece) against the oracle's dual-
+    number pass through the network, per path, FP64."""
+    pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 16, 5, 4096, K=1.0)
+    g, pp = S.adjoint(pr, H, prec="pwl64", seed=42, payoff=payoff, ckpt_every=4, per_path=True)
+    pp = pp.cpu().numpy()
+    f, df = oracle_pathwise(pr, Ho, 42, payoff, pr.N)
+    assert np.max(np.abs(pp[:, 0] - f)) <= 1e-12 * (1 + np.max(np.abs(f)))
+    scale = 1 + np.max(np.abs(df), axis=0)
+    err = np.max(np.abs(pp[:, 1:] - df), axis=0) / scale
+    print("pwl64", payoff, "max pathwise gradient error", err)
+    assert np.all(err <= 1e-10)
+
+
+def test_piecewise_linear_adjoint_fp32_and_checkpoints(S, H):
+    pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 16, 5, 20_000, K=1.0)
+    ref = S.adjoint(pr, H, prec="pwl64", seed=5, payoff=1, ckpt_every=4)
+    for k in (1, 7):
+        assert S.adjoint(pr, H, prec="pwl64", seed=5, payoff=1, ckpt_every=k) == ref
+    g32 = S.adjoint(pr, H, prec="pwl32", seed=5, payoff=1, ckpt_every=4)
+    for q in range(3):
+        assert abs(g32["grad"][q] - ref["grad"][q]) <= 1e-4 * abs(ref["grad"][q]) + 1e-6
+
+
+def test_piecewise_linear_adjoint_on_cir(S):
+    """CIR (three parameters, zero clamp) through the compiled form against
+    the network's own lane back-propagation, per path, FP64."""
+    Hc = S.Mlp.load(os.path.join(ROOT, "tests", "golden", "cir_mlp_5x64.sl7w"))
+    d = W.cir_instances(4)[2]
+    pr = S.Problem(d["model"], d["theta"], d["Y0"], d["T"], d["M"], d["m"], 3000, K=d["theta"][1])
+    _, a = S.adjoint(pr, Hc, prec="pwl64", seed=9, payoff=1, ckpt_every=4, per_path=True)
+    _, b = S.adjoint(pr, Hc, prec="f64", seed=9, payoff=1, ckpt_every=4, per_path=True)
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    scale = 1 + np.max(np.abs(b), axis=0)
+    assert np.all(np.max(np.abs(a - b), axis=0) / scale <= 1e-10)
