@@ -8,7 +8,8 @@
 //   piece    p = number of breakpoints <= Y, from a uniform grid over the
 //            breakpoints (one cell load) and a short scan either way
 //   H        y_j = c_j + a_j (Y - o)              (m FMAs, the piece's record)
-//   g_m(X)   barycentric interpolation, second form, exact-node branch
+//   g_m(X)   barycentric interpolation (weights multiplied through by the
+//            node polynomial: one division per step, exact at the nodes)
 // and the same Philox normals, clamping, domain counting and fixed-order
 // 64-path block sums as the other simulation kernels.  Work is 64-path
 // blocks of all instances from the shared work queue.
@@ -20,69 +21,58 @@
 
 namespace sl7 {
 
-template <typename T>
-__device__ __forceinline__ T interp_lane(const T* xs, const T* ls, int m, const T* y, T X) {
-  if constexpr (sizeof(T) == 8) {
-    T num = 0.0, den = 0.0, yh = 0.0;
-    bool hit = false;
+// Barycentric interpolation through the MM nodes, with the weights of the
+// second form multiplied through by l(X) = prod_k (X - x_k):
+// g = sum_j t_j y_j / sum_j t_j, t_j = lambda_j prod_{k != j} (X - x_k),
+// the products from prefix and suffix runs.  Same quotient as
+// sum_j (lambda_j / (X - x_j)) y_j / sum_j lambda_j / (X - x_j), with one
+// division instead of MM; at a node X = x_j every other t_k is 0 and the
+// quotient is y_j exactly, so no branch is needed.
+template <typename T, int MM>
+__device__ __forceinline__ T interp_lane(const T* xs, const T* ls, const T* y, T X) {
+  T d[MM], pre[MM];
 #pragma unroll
-    for (int j = 0; j < kMaxM; ++j) {
-      if (j < m) {
-        if (X == xs[j]) { hit = true; yh = y[j]; }
-        const T t = ls[j] / (X - xs[j]);
-        num = fma(t, y[j], num);
-        den += t;
-      }
-    }
-    return hit ? yh : num / den;
-  } else {
-    // At a node X - x_j == 0 becomes 1e-30: that weight then exceeds the
-    // others by ~28 orders of magnitude and the quotient is y_j to FP32
-    // rounding, without a branch.
-    float num = 0.f, den = 0.f;
+  for (int j = 0; j < MM; ++j) d[j] = X - xs[j];
+  pre[0] = T(1);
 #pragma unroll
-    for (int j = 0; j < kMaxM; ++j) {
-      if (j < m) {
-        float d = X - xs[j];
-        d = d == 0.f ? 1e-30f : d;
-        const float t = ls[j] * fast_rcp(d);
-        num = fmaf(t, y[j], num);
-        den += t;
-      }
-    }
-    return num * fast_rcp(den);
+  for (int j = 1; j < MM; ++j) pre[j] = pre[j - 1] * d[j - 1];
+  T suf = T(1), num = T(0), den = T(0);
+#pragma unroll
+  for (int j = MM - 1; j >= 0; --j) {
+    const T t = ls[j] * (pre[j] * suf);
+    num = fma(t, y[j], num);
+    den += t;
+    suf *= d[j];
   }
+  if constexpr (sizeof(T) == 8) return num / den; else return num * fast_rcp(den);
 }
 
 // Slopes and anchor values of a piece record with 16-byte loads (the record
-// is 16-byte aligned; entries beyond m are never used).
-template <typename T>
-__device__ __forceinline__ void load_record(const T* __restrict__ rec, int m, T* sl, T* va) {
+// is 16-byte aligned).
+template <typename T, int MM>
+__device__ __forceinline__ void load_record(const T* __restrict__ rec, T* sl, T* va) {
   typedef float f4 __attribute__((ext_vector_type(4)));
   typedef double d2 __attribute__((ext_vector_type(2)));
   constexpr int per = 16 / (int)sizeof(T);  // entries per 16-byte load
 #pragma unroll
-  for (int q = 0; q < kMaxM / per; ++q) {
-    if (q * per < m) {
-      if constexpr (sizeof(T) == 4) {
-        const f4 a = reinterpret_cast<const f4*>(rec)[q];
-        const f4 c = reinterpret_cast<const f4*>(rec + kMaxM)[q];
+  for (int q = 0; q * per < MM; ++q) {
+    if constexpr (sizeof(T) == 4) {
+      const f4 a = reinterpret_cast<const f4*>(rec)[q];
+      const f4 c = reinterpret_cast<const f4*>(rec + kMaxM)[q];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) { sl[4 * q + e] = a[e]; va[4 * q + e] = c[e]; }
-      } else {
-        const d2 a = reinterpret_cast<const d2*>(rec)[q];
-        const d2 c = reinterpret_cast<const d2*>(rec + kMaxM)[q];
-#pragma unroll
-        for (int e = 0; e < 2; ++e) { sl[2 * q + e] = a[e]; va[2 * q + e] = c[e]; }
-      }
+      for (int e = 0; e < 4; ++e)
+        if (4 * q + e < MM) { sl[4 * q + e] = a[e]; va[4 * q + e] = c[e]; }
     } else {
+      const d2 a = reinterpret_cast<const d2*>(rec)[q];
+      const d2 c = reinterpret_cast<const d2*>(rec + kMaxM)[q];
 #pragma unroll
-      for (int e = 0; e < per; ++e) { sl[per * q + e] = T(0); va[per * q + e] = T(0); }
+      for (int e = 0; e < 2; ++e)
+        if (2 * q + e < MM) { sl[2 * q + e] = a[e]; va[2 * q + e] = c[e]; }
     }
   }
 }
 
-template <typename T>
+template <typename T, int MM>
 __device__ __forceinline__ void pwl_block(const SimArgs& a, const InstDev& I, int64_t blk,
                                           const T* xs, const T* ls, int lane) {
   constexpr bool F64 = sizeof(T) == 8;
@@ -92,7 +82,8 @@ __device__ __forceinline__ void pwl_block(const SimArgs& a, const InstDev& I, in
   const bool valid = p < I.N;
   const int64_t gp = I.path_offset + p;
   const uint32_t tag = (uint32_t)I.tag;
-  const int M = I.M, m = a.m;
+  const int M = I.M;
+  const bool clamp = I.clamp_zero != 0;
   const T dlo = F64 ? (T)I.dom_lo : (T)I.dom_lo_f;
   const T dhi = F64 ? (T)I.dom_hi : (T)I.dom_hi_f;
   T Y = F64 ? (T)I.Y0 : (T)I.Y0_f;
@@ -106,14 +97,13 @@ __device__ __forceinline__ void pwl_block(const SimArgs& a, const InstDev& I, in
       if (i0 + u < M) {
         if (Y < dlo || Y > dhi) ++ood;
         const T* __restrict__ rec = rec0 + (int64_t)pwl_piece<T>(base, I, Y) * kPwlStride;
-        T sl[kMaxM], va[kMaxM];
-        load_record<T>(rec, m, sl, va);
+        T sl[MM], va[MM], y[MM];
+        load_record<T, MM>(rec, sl, va);
         const T dY = Y - rec[2 * kMaxM];
-        T y[kMaxM];
 #pragma unroll
-        for (int j = 0; j < kMaxM; ++j) y[j] = j < m ? fma(sl[j], dY, va[j]) : T(0);
-        Y = interp_lane<T>(xs, ls, m, y, xq[u]);
-        if (I.clamp_zero && Y < T(0)) { Y = T(0); ++clamped; }
+        for (int j = 0; j < MM; ++j) y[j] = fma(sl[j], dY, va[j]);
+        Y = interp_lane<T, MM>(xs, ls, y, xq[u]);
+        if (clamp && Y < T(0)) { Y = T(0); ++clamped; }
       }
     }
   }
@@ -123,13 +113,13 @@ __device__ __forceinline__ void pwl_block(const SimArgs& a, const InstDev& I, in
   block_partial(f0, f1, valid ? clamped : 0, valid ? ood : 0, a.partials + I.part_offset + blk);
 }
 
-template <typename T>
+template <typename T, int MM>
 __global__ __launch_bounds__(256) void k_sim_pwl(SimArgs a) {
   constexpr bool F64 = sizeof(T) == 8;
   const int lane = threadIdx.x & 63;
-  T xs[kMaxM], ls[kMaxM];
+  T xs[MM], ls[MM];
 #pragma unroll
-  for (int j = 0; j < kMaxM; ++j) {
+  for (int j = 0; j < MM; ++j) {
     xs[j] = F64 ? (T)a.xd[j] : (T)a.xs[j];
     ls[j] = F64 ? (T)a.ld[j] : (T)a.ls[j];
   }
@@ -140,19 +130,30 @@ __global__ __launch_bounds__(256) void k_sim_pwl(SimArgs a) {
     for (uint64_t item = item0; item < end; ++item) {
       int64_t blk;
       const InstDev* I = locate(a, item, blk);
-      pwl_block<T>(a, *I, blk, xs, ls, lane);
+      pwl_block<T, MM>(a, *I, blk, xs, ls, lane);
     }
   }
+}
+
+template <typename T>
+static hipError_t launch_m(const SimArgs& a, dim3 g, dim3 b, hipStream_t s) {
+  switch (a.m) {
+    case 2: hipLaunchKernelGGL((k_sim_pwl<T, 2>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_sim_pwl<T, 3>), g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_sim_pwl<T, 4>), g, b, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_sim_pwl<T, 5>), g, b, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_sim_pwl<T, 6>), g, b, 0, s, a); break;
+    case 7: hipLaunchKernelGGL((k_sim_pwl<T, 7>), g, b, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_sim_pwl<T, 8>), g, b, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_sim_pwl(int prec, const SimArgs& a, int grid, int waves_per_block,
                           hipStream_t s) {
   const dim3 g((unsigned)grid), b((unsigned)(64 * waves_per_block));
-  if (prec == SL7_PWL64)
-    hipLaunchKernelGGL(k_sim_pwl<double>, g, b, 0, s, a);
-  else
-    hipLaunchKernelGGL(k_sim_pwl<float>, g, b, 0, s, a);
-  return hipGetLastError();
+  return prec == SL7_PWL64 ? launch_m<double>(a, g, b, s) : launch_m<float>(a, g, b, s);
 }
 
 }  // namespace sl7
