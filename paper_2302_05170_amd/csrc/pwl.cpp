@@ -17,8 +17,10 @@
 #include <cstring>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
+#include "pwl_device.hpp"
 #include "sl7_host.hpp"
 #include "sl7_pwl.hpp"
 
@@ -174,32 +176,81 @@ int compile_pwl(const Mlp& H, const sl7_problem& pr, int max_pieces, PwlPieces& 
   return SL7_OK;
 }
 
-// Uniform lookup grid: cell g starts at piece start[g] = number of
-// breakpoints <= the cell's left edge, so a lookup is one cell index and a
-// short scan.  The grid spans the breakpoints from rank 2 % to rank 98 %:
-// a few far-out breakpoints (units that switch at |Y| in the hundreds) would
-// otherwise stretch the cells until each held dozens; a Y beyond the span
-// starts from the end cell and scans past at most those 2 %.
-void build_grid(const PwlPieces& pw, int cells, std::vector<int32_t>& start, double& g0,
-                double& inv_h) {
-  start.clear();
+// Uniform lookup grid over the breakpoints from rank 2 % to rank 98 % (a few
+// far-out breakpoints -- units that switch at |Y| in the hundreds -- would
+// otherwise stretch the cells until each held dozens).  8 cells per
+// breakpoint, rounded up to a power of two.
+void grid_shape(const PwlPieces& pw, int& cells, double& g0, double& inv_h) {
+  cells = 0;
   g0 = 0.0;
   inv_h = 0.0;
   if (pw.P < 2) return;
   const int nb = (int)pw.brk.size();
+  cells = (int)std::min<int64_t>(65536, std::max<int64_t>(16, (int64_t)1 << (int)std::ceil(std::log2(8.0 * nb))));
   const double lo = pw.brk[(size_t)(0.02 * (nb - 1))];
   const double hi = pw.brk[(size_t)std::ceil(0.98 * (nb - 1))];
   const double h = (hi > lo) ? (hi - lo) / cells : 1.0;
   g0 = lo;
   inv_h = 1.0 / h;
-  start.resize(cells);
-  size_t k = 0;
-  for (int g = 0; g < cells; ++g) {
-    const double e = lo + g * h;
-    while (k < pw.brk.size() && pw.brk[k] <= e) ++k;
-    start[g] = (int32_t)k;
-  }
 }
+
+namespace {
+
+// The cell records in the lane type T.  Each cell's range of T values of Y
+// is found exactly from the device's own cell arithmetic (pwl_cell is
+// monotone in Y), so one cell record gives the exact count of breakpoints
+// below Y whenever the cell holds at most one.
+template <typename T>
+int fill_cells(const PwlPieces& pw, int G, double g0d, double ihd, char* out) {
+  const T g0 = (T)g0d, ih = (T)ihd;
+  std::vector<T> brk(pw.brk.size());
+  for (size_t k = 0; k < brk.size(); ++k) brk[k] = (T)pw.brk[k];
+  // lo[c]: smallest T with cell >= c (lo[0] = -inf, lo[G] = +inf)
+  std::vector<T> lo(G + 1);
+  lo[0] = -INFINITY;
+  lo[G] = INFINITY;
+  // bisection over the ordered bit patterns of T between -inf (cell 0) and
+  // +inf (cell G-1): near Y = 0 the floats are far denser than the rounding
+  // of Y - g0 resolves, so stepping one value at a time can take millions
+  // of steps
+  typedef typename std::conditional<sizeof(T) == 8, int64_t, int32_t>::type I;
+  const I sign = (I)((uint64_t)1 << (8 * sizeof(T) - 1));
+  auto key = [&](T y) {
+    I u;
+    std::memcpy(&u, &y, sizeof(T));
+    return u >= 0 ? (int64_t)u : -(int64_t)(u & ~sign);
+  };
+  auto val = [&](int64_t k) {
+    const I u = k >= 0 ? (I)k : (I)((-k) | (int64_t)(uint64_t)sign);
+    T y;
+    std::memcpy(&y, &u, sizeof(T));
+    return y;
+  };
+  for (int c = 1; c < G; ++c) {
+    int64_t a = key((T)-INFINITY), b = key((T)INFINITY);  // cell(a) < c <= cell(b)
+    for (;;) {
+      // floor((a + b) / 2) without overflow (b - a exceeds INT64_MAX for double)
+      const int64_t mid = (a & b) + ((a ^ b) >> 1);
+      if (mid == a) break;
+      if (pwl_cell<T>(val(mid), g0, ih, G) >= c) b = mid; else a = mid;
+    }
+    lo[c] = val(b);
+  }
+  PwlCell<T>* cells = reinterpret_cast<PwlCell<T>*>(out);
+  for (int c = 0; c < G; ++c) {
+    const int s = (int)(std::lower_bound(brk.begin(), brk.end(), lo[c]) - brk.begin());
+    const int e = (int)(std::lower_bound(brk.begin(), brk.end(), lo[c + 1]) - brk.begin());
+    PwlCell<T> r;
+    std::memset(&r, 0, sizeof(r));
+    r.s = s;
+    r.n = e - s;
+    r.b = e > s ? brk[s] : (T)0;
+    std::memcpy(&cells[c], &r, sizeof(r));
+  }
+  return SL7_OK;
+}
+
+}  // namespace
 
 // The form depends on the instance only through the model, dt and theta.
 static std::array<double, 5> pwl_key(const sl7_problem& pr) {
@@ -269,16 +320,14 @@ int build_pwl_tables(const sl7_problem* prs, int n, Mlp* H, bool f64, bool with_
   std::vector<char> buf;
   for (int k = 0; k < n; ++k) {
     const PwlPieces& P = *pw[k];
-    std::vector<int32_t> start;
+    int cells;
     double g0, ih;
-    const int cells = P.P < 2 ? 0 : (int)std::min<int64_t>(
-        65536, std::max<int64_t>(16, (int64_t)1 << (int)std::ceil(std::log2(8.0 * (P.P - 1)))));
-    build_grid(P, cells, start, g0, ih);
+    grid_shape(P, cells, g0, ih);
     InstDev& I = inst[k];
     const size_t rec = align256(buf.size());
     const size_t brk = align256(rec + (size_t)P.P * stride * el);
     const size_t grid = align256(brk + (size_t)std::max(P.P - 1, 0) * el);
-    const size_t end = align256(grid + start.size() * sizeof(int32_t));
+    const size_t end = align256(grid + (size_t)cells * 16);
     buf.resize(end, 0);
     for (int p = 0; p < P.P; ++p) {
       const size_t r = rec + (size_t)p * stride * el;
@@ -308,7 +357,11 @@ int build_pwl_tables(const sl7_problem* prs, int n, Mlp* H, bool f64, bool with_
     for (int q = 0; q + 1 < P.P; ++q) {
       if (f64) put(buf, brk + q * el, P.brk[q]); else put(buf, brk + q * el, (float)P.brk[q]);
     }
-    if (!start.empty()) std::memcpy(buf.data() + grid, start.data(), start.size() * sizeof(int32_t));
+    if (cells > 0) {
+      const int rc = f64 ? fill_cells<double>(P, cells, g0, ih, buf.data() + grid)
+                         : fill_cells<float>(P, cells, g0, ih, buf.data() + grid);
+      if (rc) return rc;
+    }
     I.pwl_rec = (int64_t)rec;
     I.pwl_brk = (int64_t)brk;
     I.pwl_grid = (int64_t)grid;

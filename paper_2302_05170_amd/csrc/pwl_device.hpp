@@ -9,26 +9,51 @@
 
 namespace sl7 {
 
-// Index of the piece holding Y: the number of breakpoints <= Y, from the
-// instance's uniform grid (one cell load) and a short scan.
+// Cell of the uniform lookup grid for Y, computed identically on the host
+// (the host derives each cell's exact range of Y from this same arithmetic).
+template <typename T>
+__host__ __device__ __forceinline__ int pwl_cell(T Y, T g0, T ih, int G) {
+  T v = (Y - g0) * ih;
+  v = v > T(0) ? v : T(0);  // also maps NaN to cell 0
+  const T top = (T)(G - 1);
+  v = v < top ? v : top;
+  return (int)v;
+}
+
+// Grid cell record: s = number of breakpoints below the cell's range of Y,
+// n = breakpoints inside it, b = the first of those (when n >= 1); 16 bytes
+// in either precision.
+template <typename T>
+struct PwlCell;
+template <>
+struct PwlCell<float> {
+  int32_t s, n;
+  float b, pad;
+};
+template <>
+struct PwlCell<double> {
+  int32_t s, n;
+  double b;
+};
+
+// Index of the piece holding Y: the number of breakpoints <= Y.  One cell
+// load settles it when the cell holds at most one breakpoint; otherwise a
+// scan over the cell's breakpoints.
 template <typename T>
 __device__ __forceinline__ int pwl_piece(const char* __restrict__ base, const InstDev& I, T Y) {
   constexpr bool F64 = sizeof(T) == 8;
-  const int P = I.pwl_P;
-  if (P < 2) return 0;
-  const T* __restrict__ brk = (const T*)(base + I.pwl_brk);
-  const int32_t* __restrict__ grid = (const int32_t*)(base + I.pwl_grid);
+  if (I.pwl_P < 2) return 0;
   const T g0 = F64 ? (T)I.pwl_g0 : (T)I.pwl_g0_f;
   const T ih = F64 ? (T)I.pwl_ih : (T)I.pwl_ih_f;
-  T v = (Y - g0) * ih;
-  v = v > T(0) ? v : T(0);  // also maps NaN to cell 0
-  const T top = (T)(I.pwl_G - 1);
-  v = v < top ? v : top;
-  int p = grid[(int)v];
-  // the cell start is exact for the cell's left edge; rounding of Y - g0 can
-  // put Y one cell off, so scan in both directions
-  while (p < P - 1 && brk[p] <= Y) ++p;
-  while (p > 0 && brk[p - 1] > Y) --p;
+  const PwlCell<T> cell = ((const PwlCell<T>*)(base + I.pwl_grid))[pwl_cell<T>(Y, g0, ih, I.pwl_G)];
+  int p = cell.s;
+  if (cell.n == 1) {
+    p += Y >= cell.b ? 1 : 0;
+  } else if (cell.n > 1) {
+    const T* __restrict__ brk = (const T*)(base + I.pwl_brk);
+    const int end = cell.s + cell.n;
+    while (p < end && brk[p] <= Y) ++p;
+  }
   return p;
 }
 

@@ -22,8 +22,7 @@ struct PwlPieces {
 
 int compile_pwl(const Mlp& H, const sl7_problem& pr, int max_pieces, PwlPieces& out,
                 bool with_theta);
-void build_grid(const PwlPieces& pw, int cells, std::vector<int32_t>& start, double& g0,
-                double& inv_h);
+void grid_shape(const PwlPieces& pw, int& cells, double& g0, double& inv_h);
 
 // Most pieces a compiled network may have.
 constexpr int kPwlMaxPieces = 1 << 16;
