@@ -202,15 +202,23 @@ def main():
                      K=d["theta"][1], instance=d["instance"]) for d in W.cir_instances(256)]
     ps4 = sum(p.N * p.M for p in prs)
     batched = {}
+    # the tuner times candidate plans on one instance of the largest N (all
+    # instances share d_in and m, the tuner's cache key)
+    big = max(prs, key=lambda p: p.N * p.M)
     for prec in ("bf16x3", "bf16", "f32", "pwl32"):
-        S.simulate_batched(prs, Hc, prec=prec, seed=11, use_graph=True)
-        reps = 5 if prec != "f32" else 2
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            S.simulate_batched(prs, Hc, prec=prec, seed=11, use_graph=True)
-        dt = (time.perf_counter() - t0) / reps
-        batched[prec] = {"path_steps_per_s": ps4 / dt, "ms_per_launch": dt * 1e3}
-        log(f"batched {prec}: {ps4 / dt:.3e} path-steps/s ({dt * 1e3:.2f} ms per replay)")
+        tuned = S.autotune(big, Hc, prec=prec)
+        row = {"tuned_plan": tuned}
+        for name, plan in (("default", None), ("tuned", tuned)):
+            S.simulate_batched(prs, Hc, prec=prec, seed=11, plan=plan, use_graph=True)
+            reps = 5 if prec != "f32" else 2
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                S.simulate_batched(prs, Hc, prec=prec, seed=11, plan=plan, use_graph=True)
+            dt = (time.perf_counter() - t0) / reps
+            row[name] = {"path_steps_per_s": ps4 / dt, "ms_per_launch": dt * 1e3}
+            log(f"batched {prec} ({name} plan {plan}): {ps4 / dt:.3e} path-steps/s "
+                f"({dt * 1e3:.2f} ms per replay)")
+        batched[prec] = row
 
     # the network in its exact piecewise-linear form along Y (ReLU networks):
     # no GEMMs in the loop; FP32 and FP64 lane arithmetic

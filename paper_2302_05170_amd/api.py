@@ -182,6 +182,18 @@ def pwl_compile(H: Mlp, pr: Problem, max_pieces: int = 1 << 16) -> dict:
     return {"breaks": brk, "anchor": anc, "slope": slope, "value": value}
 
 
+def autotune(shape: Problem, H: Mlp, prec="bf16x3", cache_path: str | None = None,
+             stream=None) -> dict:
+    """Fastest launch plan for problems shaped like `shape` (sl7_autotune)."""
+    cp = shape.c()
+    plan = L.Plan()
+    L.check(L.lib().sl7_autotune(ctypes.byref(cp), H.handle, _prec(prec),
+                                 cache_path.encode() if cache_path else None, ctypes.byref(plan),
+                                 _stream(stream)))
+    return {"waves_per_block": plan.waves_per_block, "blocks_per_cu": plan.blocks_per_cu,
+            "grab": plan.grab}
+
+
 def simulate_batched(prs: list, H: Mlp, prec="bf16", seed: int = 11, plan: dict | None = None,
                      use_graph: bool = True, stream=None) -> list:
     """Runs sl7_simulate_batched; returns one stats dict per instance."""

@@ -232,35 +232,48 @@ extern "C" int sl7_autotune(const sl7_problem* shape, const sl7_mlp* Hc, int pre
   Workspace& ws = workspace(dev);
   std::lock_guard<std::mutex> lk(ws.mu);
   hipStream_t s = (hipStream_t)stream;
-  std::vector<sl7_plan> cands;
+  // the default plan first: a candidate must beat it by 2 % to replace it,
+  // so timing noise does not pick a plan
+  std::vector<sl7_plan> cands(1);
+  default_plan(prec, &cands[0]);
   const int wpb[] = {1, 2, 4};
-  const int bpc[] = {1, 2, 3, 4, 8};
+  const int bpc[] = {1, 2, 3, 4, 8, 16};
   const int grabs[] = {1, 4};
   for (int w : wpb)
     for (int b : bpc)
       for (int g : grabs) {
         if (w * b > 32) continue;
         sl7_plan p = {w, b, g, 0};
+        if (p.waves_per_block == cands[0].waves_per_block && p.blocks_per_cu == cands[0].blocks_per_cu &&
+            p.grab == cands[0].grab)
+          continue;
         cands.push_back(p);
       }
+  // time on at least 2^20 paths so that each launch fills the chip for
+  // several milliseconds
+  sl7_problem sh = *shape;
+  sh.N = std::max<int64_t>(shape->N, int64_t(1) << 20);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(SL7_EHIP, "hipEventCreate");
   SimArgs a;
-  rc = prepare_instances(shape, 1, H, prec, 1, nullptr, s, ws, a);
+  rc = prepare_instances(&sh, 1, H, prec, 1, nullptr, s, ws, a);
   float best = INFINITY;
-  sl7_plan bestp;
-  default_plan(prec, &bestp);
+  sl7_plan bestp = cands[0];
   for (size_t c = 0; c < cands.size() && !rc; ++c) {
-    rc = launch_instances(a, 1, shape->N, H, prec, cands[c], s, ws);  // warm-up
+    rc = launch_instances(a, 1, sh.N, H, prec, cands[c], s, ws);  // warm-up
+    float ms = INFINITY;
+    for (int t = 0; t < 2 && !rc; ++t) {  // best of two timings of three launches
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && !rc; ++r) rc = launch_instances(a, 1, sh.N, H, prec, cands[c], s, ws);
+      (void)hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SL7_EHIP, "hipEventSynchronize"); break; }
+      float t_ms = 0.f;
+      (void)hipEventElapsedTime(&t_ms, e0, e1);
+      ms = std::min(ms, t_ms);
+    }
     if (rc) break;
-    (void)hipEventRecord(e0, s);
-    for (int r = 0; r < 3 && !rc; ++r) rc = launch_instances(a, 1, shape->N, H, prec, cands[c], s, ws);
-    (void)hipEventRecord(e1, s);
-    if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SL7_EHIP, "hipEventSynchronize"); break; }
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best) { best = ms; bestp = cands[c]; }
+    if (c == 0 || ms < 0.98f * best) { best = ms; bestp = cands[c]; }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -272,7 +285,7 @@ extern "C" int sl7_autotune(const sl7_problem* shape, const sl7_mlp* Hc, int pre
     fprintf(f, "{\"key\": \"%s\", \"waves_per_block\": %d, \"blocks_per_cu\": %d, \"grab\": %d, "
                "\"ms_per_launch\": %.5f, \"N\": %lld, \"M\": %d}\n",
             key.c_str(), bestp.waves_per_block, bestp.blocks_per_cu, bestp.grab, best / 3.0,
-            (long long)shape->N, shape->M);
+            (long long)sh.N, sh.M);
     fclose(f);
   }
   return SL7_OK;
