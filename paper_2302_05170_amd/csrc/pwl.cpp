@@ -310,69 +310,88 @@ static int pwl_lookup_all(const sl7_problem* prs, int n, Mlp* H, bool with_theta
   return SL7_OK;
 }
 
-int build_pwl_tables(const sl7_problem* prs, int n, Mlp* H, bool f64, bool with_theta,
-                     std::vector<InstDev>& inst, hipStream_t stream, Workspace& ws) {
+// One instance's tables in the lane type, laid out as on the device (piece
+// records, breakpoints, grid cells; offsets from the blob's start).
+static int serialize(const PwlPieces& P, bool f64, bool with_theta, PwlBlob& B) {
   const size_t el = f64 ? sizeof(double) : sizeof(float);
   const int stride = with_theta ? kPwlAdjStride : kPwlStride;
+  grid_shape(P, B.cells, B.g0, B.ih);
+  B.P = P.P;
+  B.rec = 0;
+  B.brk = align256((size_t)P.P * stride * el);
+  B.grid = align256(B.brk + (size_t)std::max(P.P - 1, 0) * el);
+  std::vector<char>& buf = B.bytes;
+  buf.assign(align256(B.grid + (size_t)B.cells * 16), 0);
+  for (int p = 0; p < P.P; ++p) {
+    const size_t r = B.rec + (size_t)p * stride * el;
+    if (with_theta) {
+      for (int k = 0; k < P.n_theta; ++k)
+        for (int j = 0; j < P.m; ++j) {
+          const double da = P.da[((size_t)p * P.n_theta + k) * P.m + j];
+          const double db = P.db[((size_t)p * P.n_theta + k) * P.m + j];
+          const size_t oa = r + (kPwlStride + k * kMaxM + j) * el;
+          const size_t ob = r + (kPwlStride + (4 + k) * kMaxM + j) * el;
+          if (f64) { put(buf, oa, da); put(buf, ob, db); }
+          else { put(buf, oa, (float)da); put(buf, ob, (float)db); }
+        }
+    }
+    for (int j = 0; j < P.m; ++j) {
+      const double a = P.a[(size_t)p * P.m + j], c = P.c[(size_t)p * P.m + j];
+      if (f64) {
+        put(buf, r + j * el, a);
+        put(buf, r + (kMaxM + j) * el, c);
+      } else {
+        put(buf, r + j * el, (float)a);
+        put(buf, r + (kMaxM + j) * el, (float)c);
+      }
+    }
+    if (f64) put(buf, r + 2 * kMaxM * el, P.o[p]); else put(buf, r + 2 * kMaxM * el, (float)P.o[p]);
+  }
+  for (int q = 0; q + 1 < P.P; ++q) {
+    if (f64) put(buf, B.brk + q * el, P.brk[q]); else put(buf, B.brk + q * el, (float)P.brk[q]);
+  }
+  if (B.cells > 0)
+    return f64 ? fill_cells<double>(P, B.cells, B.g0, B.ih, buf.data() + B.grid)
+               : fill_cells<float>(P, B.cells, B.g0, B.ih, buf.data() + B.grid);
+  return SL7_OK;
+}
+
+int build_pwl_tables(const sl7_problem* prs, int n, Mlp* H, bool f64, bool with_theta,
+                     std::vector<InstDev>& inst, hipStream_t stream, Workspace& ws) {
   std::vector<std::shared_ptr<PwlPieces>> pw;
-  int rc0 = pwl_lookup_all(prs, n, H, with_theta, pw);
-  if (rc0) return rc0;
+  int rc = pwl_lookup_all(prs, n, H, with_theta, pw);
+  if (rc) return rc;
   std::vector<char> buf;
   for (int k = 0; k < n; ++k) {
-    const PwlPieces& P = *pw[k];
-    int cells;
-    double g0, ih;
-    grid_shape(P, cells, g0, ih);
+    PwlPieces& P = *pw[k];
+    std::shared_ptr<const PwlBlob> B;
+    {
+      // the serialized tables are cached with the compiled form
+      std::lock_guard<std::mutex> lk(P.mu);
+      std::shared_ptr<const PwlBlob>& slot = P.blob[f64 ? 1 : 0][with_theta ? 1 : 0];
+      if (!slot) {
+        std::shared_ptr<PwlBlob> nb(new PwlBlob());
+        rc = serialize(P, f64, with_theta, *nb);
+        if (rc) return rc;
+        slot = nb;
+      }
+      B = slot;
+    }
+    const size_t base = align256(buf.size());
+    buf.resize(base + B->bytes.size());
+    std::memcpy(buf.data() + base, B->bytes.data(), B->bytes.size());
     InstDev& I = inst[k];
-    const size_t rec = align256(buf.size());
-    const size_t brk = align256(rec + (size_t)P.P * stride * el);
-    const size_t grid = align256(brk + (size_t)std::max(P.P - 1, 0) * el);
-    const size_t end = align256(grid + (size_t)cells * 16);
-    buf.resize(end, 0);
-    for (int p = 0; p < P.P; ++p) {
-      const size_t r = rec + (size_t)p * stride * el;
-      if (with_theta) {
-        for (int k = 0; k < P.n_theta; ++k)
-          for (int j = 0; j < P.m; ++j) {
-            const double da = P.da[((size_t)p * P.n_theta + k) * P.m + j];
-            const double db = P.db[((size_t)p * P.n_theta + k) * P.m + j];
-            const size_t oa = r + (kPwlStride + k * kMaxM + j) * el;
-            const size_t ob = r + (kPwlStride + (4 + k) * kMaxM + j) * el;
-            if (f64) { put(buf, oa, da); put(buf, ob, db); }
-            else { put(buf, oa, (float)da); put(buf, ob, (float)db); }
-          }
-      }
-      for (int j = 0; j < P.m; ++j) {
-        const double a = P.a[(size_t)p * P.m + j], c = P.c[(size_t)p * P.m + j];
-        if (f64) {
-          put(buf, r + j * el, a);
-          put(buf, r + (kMaxM + j) * el, c);
-        } else {
-          put(buf, r + j * el, (float)a);
-          put(buf, r + (kMaxM + j) * el, (float)c);
-        }
-      }
-      if (f64) put(buf, r + 2 * kMaxM * el, P.o[p]); else put(buf, r + 2 * kMaxM * el, (float)P.o[p]);
-    }
-    for (int q = 0; q + 1 < P.P; ++q) {
-      if (f64) put(buf, brk + q * el, P.brk[q]); else put(buf, brk + q * el, (float)P.brk[q]);
-    }
-    if (cells > 0) {
-      const int rc = f64 ? fill_cells<double>(P, cells, g0, ih, buf.data() + grid)
-                         : fill_cells<float>(P, cells, g0, ih, buf.data() + grid);
-      if (rc) return rc;
-    }
-    I.pwl_rec = (int64_t)rec;
-    I.pwl_brk = (int64_t)brk;
-    I.pwl_grid = (int64_t)grid;
-    I.pwl_P = P.P;
-    I.pwl_G = cells;
-    I.pwl_g0 = g0;
-    I.pwl_ih = ih;
-    I.pwl_g0_f = (float)g0;
-    I.pwl_ih_f = (float)ih;
+    I.pwl_rec = (int64_t)(base + B->rec);
+    I.pwl_brk = (int64_t)(base + B->brk);
+    I.pwl_grid = (int64_t)(base + B->grid);
+    I.pwl_P = B->P;
+    I.pwl_G = B->cells;
+    I.pwl_g0 = B->g0;
+    I.pwl_ih = B->ih;
+    I.pwl_g0_f = (float)B->g0;
+    I.pwl_ih_f = (float)B->ih;
   }
-  int rc = ws.pwl.reserve(std::max<size_t>(buf.size(), 256));
+  rc = ws.pwl.reserve(std::max<size_t>(buf.size(), 256));
   if (rc) return rc;
   const hipError_t e = hipMemcpyAsync(ws.pwl.p, buf.data(), buf.size(), hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(piecewise-linear tables)");

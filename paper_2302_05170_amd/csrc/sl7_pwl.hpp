@@ -2,6 +2,7 @@
 #pragma once
 
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "sl7_host.hpp"
@@ -15,9 +16,20 @@ namespace sl7 {
 // dy_j/dtheta_k = da[(p n_theta + k) m + j] Y + db[(p n_theta + k) m + j]
 // on piece p (the pieces' activation pattern held fixed, as back-propagation
 // through the network holds its ReLU masks).
+// Device layout of one instance's tables (see build_pwl_tables).
+struct PwlBlob {
+  std::vector<char> bytes;
+  size_t rec = 0, brk = 0, grid = 0;
+  int P = 0, cells = 0;
+  double g0 = 0.0, ih = 0.0;
+};
+
 struct PwlPieces {
   int P = 0, m = 0, n_theta = 0;
   std::vector<double> brk, o, a, c, da, db;
+  // serialized tables by [FP64][with theta], built on first use
+  std::mutex mu;
+  std::shared_ptr<const PwlBlob> blob[2][2];
 };
 
 int compile_pwl(const Mlp& H, const sl7_problem& pr, int max_pieces, PwlPieces& out,
