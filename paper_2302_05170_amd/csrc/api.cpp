@@ -130,6 +130,43 @@ int DevBuf::reserve(size_t n) {
   return SL7_OK;
 }
 
+Staging::~Staging() {
+  if (pending && ev) (void)hipEventSynchronize(ev);
+  if (ev) (void)hipEventDestroy(ev);
+  if (p) (void)hipHostFree(p);
+}
+
+int Staging::acquire(size_t n) {
+  if (pending) {
+    const hipError_t e = hipEventSynchronize(ev);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(staging)");
+    pending = false;
+  }
+  if (!ev) {
+    const hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate(staging)");
+  }
+  if (n <= bytes) return SL7_OK;
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  bytes = 0;
+  const hipError_t e = hipHostMalloc(&p, n, 0);
+  if (e != hipSuccess) {
+    p = nullptr;
+    return fail(SL7_ENOMEM, "hipHostMalloc(%zu): %s", n, hipGetErrorString(e));
+  }
+  bytes = n;
+  return SL7_OK;
+}
+
+int Staging::upload(void* dst, size_t off, size_t n, hipStream_t stream, const char* what) {
+  hipError_t e = hipMemcpyAsync(dst, (const char*)p + off, n, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipEventRecord(ev, stream);
+  if (e != hipSuccess) return hip_fail(e, what);
+  pending = true;
+  return SL7_OK;
+}
+
 Workspace& workspace(int dev) {
   static std::mutex mu;
   static std::map<int, std::unique_ptr<Workspace>> all;
@@ -587,10 +624,20 @@ int prepare_instances(const sl7_problem* prs, int n, const Mlp* H, int prec, uin
   if (!rc) rc = ws.stats.reserve(sizeof(sl7_stats) * n);
   if (!rc) rc = ws.chunks.reserve(finalize_scratch_bytes(n));
   if (rc) return rc;
-  hipError_t e = hipMemcpyAsync(ws.inst.p, inst.data(), sizeof(InstDev) * n, hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(ws.prefix.p, prefix.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(ws.order.p, order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream);
+  // one staged upload: instance table, then work-order prefix sums and order
+  const size_t b_inst = sizeof(InstDev) * n, b_pre = sizeof(int64_t) * (n + 1);
+  const size_t b_ord = sizeof(int32_t) * n;
+  rc = ws.stage_inst.acquire(b_inst + b_pre + b_ord);
+  if (rc) return rc;
+  char* h = (char*)ws.stage_inst.p;
+  std::memcpy(h, inst.data(), b_inst);
+  std::memcpy(h + b_inst, prefix.data(), b_pre);
+  std::memcpy(h + b_inst + b_pre, order.data(), b_ord);
+  hipError_t e = hipMemcpyAsync(ws.inst.p, h, b_inst, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(ws.prefix.p, h + b_inst, b_pre, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(instance table)");
+  rc = ws.stage_inst.upload(ws.order.p, b_inst + b_pre, b_ord, stream, "hipMemcpyAsync(work order)");
+  if (rc) return rc;
   a.inst = (const InstDev*)ws.inst.p;
   a.item_prefix = (const int64_t*)ws.prefix.p;
   a.order = (const int32_t*)ws.order.p;

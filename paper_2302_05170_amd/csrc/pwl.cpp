@@ -392,10 +392,10 @@ int build_pwl_tables(const sl7_problem* prs, int n, Mlp* H, bool f64, bool with_
     I.pwl_ih_f = (float)B->ih;
   }
   rc = ws.pwl.reserve(std::max<size_t>(buf.size(), 256));
+  if (!rc) rc = ws.stage_pwl.acquire(buf.size());
   if (rc) return rc;
-  const hipError_t e = hipMemcpyAsync(ws.pwl.p, buf.data(), buf.size(), hipMemcpyHostToDevice, stream);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(piecewise-linear tables)");
-  return SL7_OK;
+  std::memcpy(ws.stage_pwl.p, buf.data(), buf.size());
+  return ws.stage_pwl.upload(ws.pwl.p, 0, buf.size(), stream, "hipMemcpyAsync(piecewise-linear tables)");
 }
 
 }  // namespace sl7

@@ -34,12 +34,33 @@ struct DevBuf {
   int reserve(size_t n);
 };
 
+// Pinned host staging for host-to-device uploads.  An upload enqueued from
+// it may still be in flight when the call returns; the event recorded after
+// it is waited on before the buffer is written again or freed.
+struct Staging {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+  Staging() = default;
+  Staging(const Staging&) = delete;
+  Staging& operator=(const Staging&) = delete;
+  ~Staging();
+  // waits for the previous upload, then makes room for n bytes
+  int acquire(size_t n);
+  // enqueues the upload of n bytes from offset off to dst on stream and
+  // records the event (which then also covers earlier uploads from this
+  // buffer on the same stream)
+  int upload(void* dst, size_t off, size_t n, hipStream_t stream, const char* what);
+};
+
 // Scratch of one device, shared by the calls made on it (serialised by mu).
 struct Workspace {
   std::mutex mu;
   int n_cu = 0;
   DevBuf inst, prefix, order, counter, partials, stats, chunks;
   DevBuf pwl;     // piecewise-linear tables of the instances (PWL modes)
+  Staging stage_inst, stage_pwl;
   DevBuf aux[8];  // adjoint checkpoints, trainer buffers, ...
   sl7_stats* stats_host = nullptr;
   int stats_host_n = 0;
