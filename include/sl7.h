@@ -196,7 +196,8 @@ int sl7_simulate(const sl7_problem* pr, const sl7_mlp* H, int prec,
  * non-NULL (host arrays of P-1, P, P*m and P*m doubles) they receive the
  * breakpoints (ascending; piece p covers [brk[p-1], brk[p])), the anchors
  * o_p and, for output j, y_j = value[p*m+j] + slope[p*m+j] (Y - o_p).  Pass
- * them all NULL to query P.  max_pieces caps P (EUNSUPPORTED beyond it).
+ * them all NULL to query P.  max_pieces in [1, 65536] caps P
+ * (EUNSUPPORTED beyond it; EINVAL for max_pieces outside that range).
  * No device work. */
 int sl7_pwl_compile(const sl7_mlp* H, const sl7_problem* pr, int max_pieces, int* n_pieces,
                     double* brk, double* anchor, double* slope, double* value);

@@ -409,7 +409,8 @@ extern "C" int sl7_pwl_compile(const sl7_mlp* Hc, const sl7_problem* pr, int max
   if (!n_pieces) return fail(SL7_EINVAL, "n_pieces is NULL");
   int rc = check_problem(pr, H, SL7_PWL64, "pr");
   if (rc) return rc;
-  if (max_pieces < 1) return fail(SL7_EINVAL, "max_pieces=%d must be >= 1", max_pieces);
+  if (max_pieces < 1 || max_pieces > kPwlMaxPieces)
+    return fail(SL7_EINVAL, "max_pieces=%d outside [1, %d]", max_pieces, kPwlMaxPieces);
   const bool all = brk && anchor && slope && value;
   if (!all && (brk || anchor || slope || value))
     return fail(SL7_EINVAL, "brk, anchor, slope and value must all be NULL or all non-NULL");

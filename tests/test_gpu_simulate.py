@@ -228,3 +228,26 @@ def test_eval_H_matches_oracle_forward(S, H, Ho, prec):
     # (the split BF16 form drops lo*lo, ~2^-16 of each product)
     tol = {"f64": 1.2e-7, "f32": 1e-5, "bf16": 2e-2, "f16": 5e-3, "bf16x3": 1e-4, "f16x3": 1e-5}[prec]
     assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 0.1)) <= tol
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "f16x3", "bf16", "f16", "pwl32", "pwl64"])
+def test_degenerate_shapes(S, H, Ho, prec):
+    """One step (M = 1), one path, a single 64-path block exactly, and the
+    largest step of the training range, in every mode."""
+    c = W.CONFIGS["c1"]
+    tol = {"pwl32": TOL["f32"], "pwl64": TOL["f64"]}.get(prec, TOL.get(prec))
+    for T, M, N in ((0.5, 1, 1), (0.5, 1, 64), (1.0, 2, 129), (0.05, 1, 777)):
+        pr = S.Problem(c["model"], c["theta"], c["Y0"], T, M, c["m"], N, K=c["K"])
+        ref = orc(pr, Ho, 21, np.arange(N))
+        st, y = gpu_yt(S, pr, H, prec, 21)
+        assert st["n"] == N
+        assert rel(y, ref).max() <= tol, (prec, T, M, N)
+
+
+@pytest.mark.parametrize("m", [2, 8])
+def test_analytic_extreme_node_counts_single_step(S, m):
+    pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 0.25, 1, m, 1000, K=1.0)
+    ref = orc(pr, None, 8, np.arange(pr.N))
+    for prec in ("f64", "f32"):
+        st, y = gpu_yt(S, pr, None, prec, 8)
+        assert rel(y, ref).max() <= TOL[prec], (m, prec)

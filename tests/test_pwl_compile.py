@@ -131,6 +131,10 @@ def test_limits_and_rejections(S):
     with pytest.raises(S.Sl7Error) as e:
         S.pwl_compile(H, pr, max_pieces=10)
     assert e.value.code == L.SL7_EUNSUPPORTED
+    for bad in (0, (1 << 16) + 1):
+        with pytest.raises(S.Sl7Error) as e:
+            S.pwl_compile(H, pr, max_pieces=bad)
+        assert e.value.code == L.SL7_EINVAL
     ou = S.Problem(W.OU, (0.5, 0.3, 1.0), 0.2, 2.0, 8, 5, 100)
     with pytest.raises(S.Sl7Error) as e:
         S.pwl_compile(S.Mlp.load(OU_W), ou)
