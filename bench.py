@@ -46,22 +46,27 @@ ISSUED["bf16x3"] = ISSUED["f16x3"] = 3 * ISSUED["bf16"]
 PROFILE_X3 = os.path.join(ROOT, "profiles", "k_sim_mfma_x3_bf16x3_gbm_N2e24_M32.md")
 
 
-def profiled_traffic(path=PROFILE_X3):
-    """HBM bytes per launch of the headline kernel from the committed
-    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel sources have
-    changed since those counters were taken."""
+def profiled(field, path=PROFILE_X3):
+    """A figure of the headline kernel from its committed rocprofv3 summary
+    (HBM bytes per launch from FETCH_SIZE / WRITE_SIZE, MFMA busy fraction
+    from SQ counters), or None when the kernel sources have changed since
+    those counters were taken."""
     import hashlib
     try:
         fields = dict(l.split(": ", 1) for l in open(path).read().splitlines()
-                      if l.startswith(("traffic_bytes_per_launch:", "source_sha256:", "source_files:")))
+                      if l.startswith((field + ":", "source_sha256:", "source_files:")))
         h = hashlib.sha256()
         for f in fields["source_files"].split():
             h.update(open(os.path.join(ROOT, f), "rb").read())
         if h.hexdigest() != fields["source_sha256"]:
             return None
-        return float(fields["traffic_bytes_per_launch"])
+        return float(fields[field])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def profiled_traffic(path=PROFILE_X3):
+    return profiled("traffic_bytes_per_launch", path)
 
 
 def log(msg):
@@ -291,6 +296,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["bf16"] / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK["bf16"],
                      "traffic": profiled_traffic()},
+        "mfma_busy_rocprof": profiled("mfma_busy_fraction"),
         "precision_compare": {
             p: {"path_steps_per_s": ps / r["wall"], "kernel_ms": r["ev_async"] * 1e3,
                 "frac_of_dtype_peak": FLOPS_PER_PATH_STEP * ps / r["ev_async"] / PEAK[p],
