@@ -105,109 +105,164 @@ hipError_t launch_em_labels(const LabelArgs& a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Training: forward + backward of 64 samples per workgroup (one per lane),
-// FP32.  Parameter layout: per layer W (out x in, row-major) then b.
+// Training: forward + backward of 64 samples per workgroup on FP32 MFMA
+// (v_mfma_f32_16x16x4_f32).  Four waves; in every product the 64 samples
+// are four 16-column tiles.  Parameter layout: per layer W (out x in,
+// row-major) then b; hidden layers l = 0..3 give H_{l+1} = ReLU(W_l H_l +
+// b_l), the head y = W_4 H_4 + b_4.
+//   forward   wave w: units 16w..16w+15 of each hidden layer, all samples;
+//             the head (m <= 8 rows, padded to 16) one sample tile per wave
+//   backward  dZ_l = (W_{l+1}^T dZ_{l+1}) * [H_{l+1} > 0], same split
+//   gradient  dW_l = dZ_l H_l^T over the 64 samples (K = samples), tiles
+//             spread over the waves; bias sums in a fixed order
+// MFMA operand layout (16x16x4): lane (g = l/16, r = l%16) gives A[r][g]
+// and B[g][r]; the result holds D[4g + i][r], i = 0..3.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_fwd_bwd(TrainArgs a, int64_t base) {
+constexpr int kTS = 65;  // LDS row stride of the [unit][sample] buffers (bank spread)
+
+__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(256) void k_fwd_bwd(TrainArgs a, int64_t base) {
   extern __shared__ float sh[];
-  // LDS: act[l][unit][lane] for l = 0..3 (hidden outputs), del[l][unit][lane]
-  float* act = sh;                     // 4 * 64 * 64
-  float* del = sh + 4 * 64 * 64;       // 4 * 64 * 64
-  float* h0 = del + 4 * 64 * 64;       // d_in * 64
-  float* dy = h0 + kMaxDinLane * 64;   // m * 64
-  const int t = threadIdx.x;
+  // H[0]: inputs [8][kTS]; H[1..4]: hidden outputs [64][kTS]; D[0..3]: dZ of
+  // hidden layers [64][kTS]; dY [8][kTS]
+  float* H[5];
+  H[0] = sh;
+  for (int l = 1; l <= 4; ++l) H[l] = sh + 8 * kTS + (l - 1) * 64 * kTS;
+  float* D[4];
+  for (int l = 0; l < 4; ++l) D[l] = sh + 8 * kTS + 4 * 64 * kTS + l * 64 * kTS;
+  float* dY = sh + 8 * kTS + 8 * 64 * kTS;
+  __shared__ float red[4];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63, g = lane >> 4, r = lane & 15;
   const int din = a.d_in, m = a.m;
-  const int64_t s = base + (int64_t)blockIdx.x * 64 + t;
-  const int64_t row = a.order ? a.order[s % a.order_len] : (s % a.n);
-  const bool valid = ((int64_t)blockIdx.x * 64 + t) < a.batch;
   const float* P = a.params;
-  // forward
-  for (int k = 0; k < din; ++k)
-    h0[k * 64 + t] = valid ? a.in_scale[k] * a.X[row * din + k] + a.in_shift[k] : 0.f;
-  int64_t off = 0;
-  int n_in = din;
-  const float* hin = h0;
+  int64_t off[5];
+  off[0] = 0;
+  off[1] = 64 * din + 64;
+  for (int l = 2; l <= 4; ++l) off[l] = off[l - 1] + 64 * 64 + 64;
+  // inputs (rows >= d_in zero)
+  for (int i = t; i < 8 * 64; i += 256) {
+    const int k = i >> 6, sidx = i & 63;
+    const int64_t s = base + (int64_t)blockIdx.x * 64 + sidx;
+    const bool valid = ((int64_t)blockIdx.x * 64 + sidx) < a.batch;
+    const int64_t row = a.order ? a.order[s % a.order_len] : (s % a.n);
+    H[0][k * kTS + sidx] = (valid && k < din) ? a.in_scale[k] * a.X[row * din + k] + a.in_shift[k] : 0.f;
+  }
+  __syncthreads();
+  // forward through the hidden layers
   for (int l = 0; l < 4; ++l) {
-    const float* W = P + off;
-    const float* b = W + 64 * n_in;
-    float* hout = act + l * 64 * 64;
-    for (int o = 0; o < 64; ++o) {
-      float z = b[o];
-      for (int k = 0; k < n_in; ++k) z = fmaf(W[o * n_in + k], hin[k * 64 + t], z);
-      hout[o * 64 + t] = z > 0.f ? z : 0.f;
+    const int nin = l == 0 ? din : 64;
+    const int kpad = l == 0 ? 8 : 64;
+    const float* W = P + off[l];
+    const float* b = W + 64 * nin;
+    const int u = 16 * w + r;  // this lane's A row (unit)
+    f32x4 acc[4];
+    for (int st = 0; st < 4; ++st)
+      for (int i = 0; i < 4; ++i) acc[st][i] = b[16 * w + 4 * g + i];
+    for (int kb = 0; kb < kpad / 4; ++kb) {
+      const int k = 4 * kb + g;
+      const float av = k < nin ? W[u * nin + k] : 0.f;
+      for (int st = 0; st < 4; ++st) acc[st] = mfma4(av, H[l][k * kTS + 16 * st + r], acc[st]);
     }
-    off += 64 * n_in + 64;
-    n_in = 64;
-    hin = hout;
+    for (int st = 0; st < 4; ++st)
+      for (int i = 0; i < 4; ++i) H[l + 1][(16 * w + 4 * g + i) * kTS + 16 * st + r] = fmaxf(acc[st][i], 0.f);
+    __syncthreads();
   }
-  const float* Wh = P + off;
-  const float* bh = Wh + 64 * m;
+  // head and residuals: wave w takes samples 16w..16w+15
   float sq = 0.f;
-  const float scale = 2.f / (float)(a.batch * m);
-  for (int j = 0; j < m; ++j) {
-    float y = bh[j];
-    for (int k = 0; k < 64; ++k) y = fmaf(Wh[j * 64 + k], hin[k * 64 + t], y);
-    const float r = valid ? y - a.Yl[row * m + j] : 0.f;
-    sq = fmaf(r, r, sq);
-    dy[j * 64 + t] = scale * r;
-  }
-  // backward: del[l] = dLoss/dz of hidden layer l
   {
-    float* d3 = del + 3 * 64 * 64;
-    const float* a3 = act + 3 * 64 * 64;
-    for (int k = 0; k < 64; ++k) {
-      float g = 0.f;
-      for (int j = 0; j < m; ++j) g = fmaf(Wh[j * 64 + k], dy[j * 64 + t], g);
-      d3[k * 64 + t] = a3[k * 64 + t] > 0.f ? g : 0.f;
+    const float* Wh = P + off[4];
+    const float* bh = Wh + 64 * m;
+    f32x4 acc;
+    for (int i = 0; i < 4; ++i) acc[i] = (4 * g + i) < m ? bh[4 * g + i] : 0.f;
+    for (int kb = 0; kb < 16; ++kb) {
+      const int k = 4 * kb + g;
+      const float av = r < m ? Wh[r * 64 + k] : 0.f;
+      acc = mfma4(av, H[4][k * kTS + 16 * w + r], acc);
     }
-  }
-  int64_t offl[4];
-  offl[0] = 0;
-  offl[1] = 64 * din + 64;
-  offl[2] = offl[1] + 64 * 64 + 64;
-  offl[3] = offl[2] + 64 * 64 + 64;
-  for (int l = 3; l >= 1; --l) {
-    const float* W = P + offl[l];
-    const float* dn = del + l * 64 * 64;
-    float* dp = del + (l - 1) * 64 * 64;
-    const float* ap = act + (l - 1) * 64 * 64;
-    for (int k = 0; k < 64; ++k) {
-      float g = 0.f;
-      for (int o = 0; o < 64; ++o) g = fmaf(W[o * 64 + k], dn[o * 64 + t], g);
-      dp[k * 64 + t] = ap[k * 64 + t] > 0.f ? g : 0.f;
+    const int sidx = 16 * w + r;
+    const int64_t s = base + (int64_t)blockIdx.x * 64 + sidx;
+    const bool valid = ((int64_t)blockIdx.x * 64 + sidx) < a.batch;
+    const int64_t row = a.order ? a.order[s % a.order_len] : (s % a.n);
+    const float scale = 2.f / (float)(a.batch * m);
+    for (int i = 0; i < 4; ++i) {
+      const int j = 4 * g + i;
+      if (j < 8) {
+        const float res = (valid && j < m) ? acc[i] - a.Yl[row * m + j] : 0.f;
+        sq = fmaf(res, res, sq);
+        dY[j * kTS + sidx] = scale * res;
+      }
     }
   }
   __syncthreads();
-  // weight gradients summed over this workgroup's 64 samples (fixed order)
+  // backward: dZ_3 from the head, then down to dZ_0
+  for (int l = 3; l >= 0; --l) {
+    const int u = 16 * w + r;  // this lane's A row: unit of layer l's output
+    f32x4 acc[4];
+    for (int st = 0; st < 4; ++st) acc[st] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (l == 3) {
+      const float* Wh = P + off[4];
+      for (int kb = 0; kb < 2; ++kb) {
+        const int j = 4 * kb + g;
+        const float av = j < m ? Wh[j * 64 + u] : 0.f;
+        for (int st = 0; st < 4; ++st) acc[st] = mfma4(av, dY[j * kTS + 16 * st + r], acc[st]);
+      }
+    } else {
+      const float* Wn = P + off[l + 1];
+      for (int kb = 0; kb < 16; ++kb) {
+        const int o = 4 * kb + g;
+        const float av = Wn[o * 64 + u];
+        for (int st = 0; st < 4; ++st) acc[st] = mfma4(av, D[l + 1][o * kTS + 16 * st + r], acc[st]);
+      }
+    }
+    for (int st = 0; st < 4; ++st)
+      for (int i = 0; i < 4; ++i) {
+        const int unit = 16 * w + 4 * g + i, sidx = 16 * st + r;
+        D[l][unit * kTS + sidx] = H[l + 1][unit * kTS + sidx] > 0.f ? acc[st][i] : 0.f;
+      }
+    __syncthreads();
+  }
+  // weight gradients of this workgroup's 64 samples: dW_l = dZ_l H_l^T
   float* G = a.partial + (int64_t)blockIdx.x * a.n_params;
   for (int l = 0; l <= 4; ++l) {
-    const int nin = (l == 0) ? din : 64;
-    const int nout = (l == 4) ? m : 64;
-    const float* dl = (l == 4) ? dy : del + l * 64 * 64;
-    const float* hl = (l == 0) ? h0 : act + (l - 1) * 64 * 64;
-    const int64_t o0 = (l == 4) ? offl[3] + 64 * 64 + 64 : offl[l];
-    for (int idx = t; idx < nout * nin + nout; idx += 64) {
-      float g = 0.f;
-      if (idx < nout * nin) {
-        const int o = idx / nin, k = idx % nin;
-        for (int q = 0; q < 64; ++q) g = fmaf(dl[o * 64 + q], hl[k * 64 + q], g);
-      } else {
-        const int o = idx - nout * nin;
-        for (int q = 0; q < 64; ++q) g += dl[o * 64 + q];
+    const int nin = l == 0 ? din : 64;
+    const int nout = l == 4 ? m : 64;
+    const int n_ob = l == 4 ? 1 : 4, n_ib = l == 0 ? 1 : 4;
+    const float* dz = l == 4 ? dY : D[l];
+    for (int tile = w; tile < n_ob * n_ib; tile += 4) {
+      const int ob = tile / n_ib, ib = tile % n_ib;
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      const int out = 16 * ob + r, in = 16 * ib + r;
+      for (int kb = 0; kb < 16; ++kb) {
+        const int sidx = 4 * kb + g;
+        const float av = out < nout ? dz[out * kTS + sidx] : 0.f;
+        const float bv = in < (l == 0 ? 8 : 64) ? H[l][in * kTS + sidx] : 0.f;
+        acc = mfma4(av, bv, acc);
       }
-      G[o0 + idx] = g;
+      for (int i = 0; i < 4; ++i) {
+        const int o = 16 * ob + 4 * g + i;
+        if (o < nout && in < nin) G[off[l] + (int64_t)o * nin + in] = acc[i];
+      }
     }
   }
-  // loss partial
-  float* red = h0;  // reuse
-  __syncthreads();
-  red[t] = sq;
-  __syncthreads();
-  if (t == 0) {
-    double tot = 0.0;
-    for (int q = 0; q < 64; ++q) tot += red[q];
-    a.loss_partial[blockIdx.x] = tot;
+  // bias gradients: fixed-order sums over the samples
+  for (int q = t; q < 4 * 64 + m; q += 256) {
+    const int l = q < 256 ? q / 64 : 4;
+    const int o = q < 256 ? q % 64 : q - 256;
+    const float* dz = l == 4 ? dY : D[l];
+    float sacc = 0.f;
+    for (int sidx = 0; sidx < 64; ++sidx) sacc += dz[o * kTS + sidx];
+    const int nin = l == 0 ? din : 64;
+    const int nout = l == 4 ? m : 64;
+    G[off[l] + (int64_t)nout * nin + o] = sacc;
   }
+  // loss partial: per-wave butterfly, then the four waves in order
+  for (int o = 32; o >= 1; o >>= 1) sq += __shfl_xor(sq, o);
+  if (lane == 0) red[w] = sq;
+  __syncthreads();
+  if (t == 0) a.loss_partial[blockIdx.x] = (double)red[0] + red[1] + red[2] + red[3];
 }
 
 // Sums the per-workgroup gradients in order; applies Adam (or only stores the
@@ -238,10 +293,11 @@ __global__ __launch_bounds__(256) void k_adam(TrainArgs a, int step, int n_wg) {
   a.params[p] -= (float)a.lr * mhat / (sqrtf(vhat) + (float)a.eps);
 }
 
+static constexpr size_t kTrainLds = sizeof(float) * (8 * kTS + 8 * 64 * kTS + 8 * kTS);
+
 hipError_t launch_train_step(const TrainArgs& a, int step, int64_t base, hipStream_t s) {
   const int n_wg = (int)((a.batch + 63) / 64);
-  const size_t lds = sizeof(float) * (8 * 64 * 64 + kMaxDinLane * 64 + kMaxM * 64);
-  hipLaunchKernelGGL(k_fwd_bwd, dim3(n_wg), dim3(64), lds, s, a, base);
+  hipLaunchKernelGGL(k_fwd_bwd, dim3(n_wg), dim3(256), kTrainLds, s, a, base);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_adam, dim3((unsigned)((a.n_params + 255) / 256)), dim3(256), 0, s, a, step,
@@ -250,9 +306,8 @@ hipError_t launch_train_step(const TrainArgs& a, int step, int64_t base, hipStre
 }
 
 hipError_t train_lds_attr() {
-  const size_t lds = sizeof(float) * (8 * 64 * 64 + kMaxDinLane * 64 + kMaxM * 64);
   return hipFuncSetAttribute((const void*)k_fwd_bwd, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds);
+                             (int)kTrainLds);
 }
 
 }  // namespace sl7
