@@ -137,7 +137,7 @@ def main():
                          "otherwise)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
               "paths shard by global index, but no multi-GPU path is built", file=sys.stderr)
         sys.exit(2)
 
@@ -152,7 +152,7 @@ def main():
     import oracle
     Ho = oracle.load_mlp(WEIGHTS)
 
-    c = W.CONFIGS["c2"]
+    c = W.CONFIGS["gbm_mlp_2p24x32"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
     ps = c["N"] * c["M"]
     if args.profile_run:
@@ -182,20 +182,21 @@ def main():
             f"{ev_async * 1e3:.2f} ms), mean {st['mean'][0]:.6f} +- {st['se'][0]:.1e}, "
             f"max rel err {emax:.2e} (p99 {e99:.2e}, {ns} paths)")
 
-    c1 = W.CONFIGS["c1"]
-    pr1 = S.Problem(c1["model"], c1["theta"], c1["Y0"], c1["T"], c1["M"], c1["m"], c1["N"], K=c1["K"])
-    wall1, _, st1 = time_calls(S, pr1, H, "f32", c1["seed"], max(2, args.steps // 2), 1, stats=True)
-    log(f"c1 f32: {c1['N'] * c1['M'] / wall1:.3e} path-steps/s")
+    g16 = W.CONFIGS["gbm_mlp_2p22x16"]
+    pr1 = S.Problem(g16["model"], g16["theta"], g16["Y0"], g16["T"], g16["M"], g16["m"], g16["N"],
+                    K=g16["K"])
+    wall1, _, st1 = time_calls(S, pr1, H, "f32", g16["seed"], max(2, args.steps // 2), 1, stats=True)
+    log(f"GBM 2^22 x 16 f32: {g16['N'] * g16['M'] / wall1:.3e} path-steps/s")
 
     # adjoint: pathwise Greeks of E[max(Y_T - 1, 0)] for the N = 2^22, M = 16 workload
-    c3 = W.CONFIGS["c3"]
-    pr3 = S.Problem(c3["model"], c3["theta"], c3["Y0"], c3["T"], c3["M"], c3["m"], c3["N"], K=c3["K"])
+    ga = W.CONFIGS["gbm_adjoint_2p22x16"]
+    pr3 = S.Problem(ga["model"], ga["theta"], ga["Y0"], ga["T"], ga["M"], ga["m"], ga["N"], K=ga["K"])
     adj = {}
     for prec in ("f64", "f32", "pwl64", "pwl32"):
-        S.adjoint(pr3, H, prec=prec, seed=c3["seed"], payoff=1, ckpt_every=c3["ckpt"])
+        S.adjoint(pr3, H, prec=prec, seed=ga["seed"], payoff=1, ckpt_every=ga["ckpt"])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        g = S.adjoint(pr3, H, prec=prec, seed=c3["seed"], payoff=1, ckpt_every=c3["ckpt"])
+        g = S.adjoint(pr3, H, prec=prec, seed=ga["seed"], payoff=1, ckpt_every=ga["ckpt"])
         dt = time.perf_counter() - t0
         adj[prec] = {"s_per_greek": dt / len(g["grad"]), "seconds": dt, "greeks": g["grad"],
                      "greeks_se": g["grad_se"]}
@@ -306,10 +307,10 @@ def main():
             for p, r in res.items()},
         "bf16x3_minus_f32_mean_over_se": (b["st"]["mean"][0] - res["f32"]["st"]["mean"][0]) / se_pair,
         "speedup_vs_f32_mfma": res["f32"]["wall"] / b["wall"],
-        "c1_f32_path_steps_per_s": c1["N"] * c1["M"] / wall1,
-        "adjoint_c3": adj,
-        "batched_c4": dict(batched, instances=len(prs), path_steps=ps4),
-        "piecewise_linear_c2": pwl,
+        "gbm_2p22x16_f32_path_steps_per_s": g16["N"] * g16["M"] / wall1,
+        "adjoint_gbm_2p22x16": adj,
+        "batched_cir_256": dict(batched, instances=len(prs), path_steps=ps4),
+        "piecewise_linear": pwl,
         "ou_table61_shape": dict(ou, workload=f"OU theta={W.OU_PAPER['theta']}, Y0={W.OU_PAPER['Y0']}, "
                                               f"T={W.OU_PAPER['T']}, M={W.OU_PAPER['M']}, m=5, "
                                               "MLP 5-50x4-5 Softplus") if ou else None,

@@ -78,9 +78,9 @@ def test_checkpoint_interval_does_not_change_results(S, H):
 
 
 def test_adjoint_vs_central_differences_with_crn(S, H):
-    """C3: N = 2^22, M = 16, K = 1, checkpoint every 4; bumps 1e-4 on Y0,
+    """The adjoint workload: N = 2^22, M = 16, K = 1, checkpoint every 4; bumps 1e-4 on Y0,
     sigma and mu; FP64 on both sides; gate 1e-3 relative."""
-    c = W.CONFIGS["c3"]
+    c = W.CONFIGS["gbm_adjoint_2p22x16"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
     g = S.adjoint(pr, H, prec="f64", seed=c["seed"], payoff=1, ckpt_every=c["ckpt"])
     h = 1e-4

@@ -49,7 +49,7 @@ def orc(pr, Ho, seed, paths):
 @pytest.mark.parametrize("N", [1, 63, 65, 4099])
 def test_ragged_counts_all_paths(S, prec, N):
     H, Ho = S.Mlp.load(GBM_W), oracle.load_mlp(GBM_W)
-    c = W.CONFIGS["c1"]
+    c = W.CONFIGS["gbm_mlp_2p22x16"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 7, c["m"], N, K=c["K"])
     ref, _, nood = orc(pr, Ho, 5, np.arange(N))
     st, y = gpu_yt(S, pr, H, prec, 5)
@@ -62,28 +62,28 @@ def test_ragged_counts_all_paths(S, prec, N):
 
 
 @pytest.mark.parametrize("prec", ["pwl64", "pwl32"])
-def test_c1_full_size_sampled(S, prec):
+def test_gbm_2p22x16_full_size_sampled(S, prec):
     H, Ho = S.Mlp.load(GBM_W), oracle.load_mlp(GBM_W)
-    c = W.CONFIGS["c1"]
+    c = W.CONFIGS["gbm_mlp_2p22x16"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
     st, y = gpu_yt(S, pr, H, prec, c["seed"])
     sub = W.parity_subset(c["N"])
     ref, _, _ = orc(pr, Ho, c["seed"], sub)
     r = rel(y[sub], ref)
-    print(f"C1 {prec}: max rel err {r.max():.3e} over {len(sub)} paths")
+    print(f"GBM 2^22 x 16 {prec}: max rel err {r.max():.3e} over {len(sub)} paths")
     assert r.max() <= TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["pwl64", "pwl32"])
-def test_c2_full_size_sampled(S, prec):
+def test_gbm_2p24x32_full_size_sampled(S, prec):
     H, Ho = S.Mlp.load(GBM_W), oracle.load_mlp(GBM_W)
-    c = W.CONFIGS["c2"]
+    c = W.CONFIGS["gbm_mlp_2p24x32"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
     st, y = gpu_yt(S, pr, H, prec, c["seed"])
     sub = W.parity_subset(c["N"])[::4]
     ref, _, _ = orc(pr, Ho, c["seed"], sub)
     r = rel(y[sub], ref)
-    print(f"C2 {prec}: max rel err {r.max():.3e} over {len(sub)} paths")
+    print(f"GBM 2^24 x 32 {prec}: max rel err {r.max():.3e} over {len(sub)} paths")
     assert r.max() <= TOL[prec]
     assert st["n"] == c["N"] and np.isfinite(st["mean"][0])
 
@@ -92,7 +92,7 @@ def test_pwl_and_mfma_paths_agree(S):
     """The same paths through the FP32 MFMA network and the FP32 piecewise-
     linear form differ only by FP32 rounding."""
     H = S.Mlp.load(GBM_W)
-    c = W.CONFIGS["c1"]
+    c = W.CONFIGS["gbm_mlp_2p22x16"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], 1 << 18, K=c["K"])
     _, a = gpu_yt(S, pr, H, "f32", 3)
     _, b = gpu_yt(S, pr, H, "pwl32", 3)
@@ -102,7 +102,7 @@ def test_pwl_and_mfma_paths_agree(S):
 @pytest.mark.parametrize("prec", ["pwl64", "pwl32"])
 def test_results_independent_of_launch_plan(S, prec):
     H = S.Mlp.load(GBM_W)
-    c = W.CONFIGS["c1"]
+    c = W.CONFIGS["gbm_mlp_2p22x16"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 9, c["m"], 50_001, K=c["K"])
     outs = [gpu_yt(S, pr, H, prec, 77, plan=plan)
             for plan in (None, dict(waves_per_block=1, blocks_per_cu=1, grab=1),

@@ -58,12 +58,12 @@ def orc(pr, Ho, seed, paths):
     return y
 
 
-def test_c0_f64_analytic_all_paths(S):
-    c = W.CONFIGS["c0"]
+def test_gbm_analytic_1e5x4_f64_all_paths(S):
+    c = W.CONFIGS["gbm_analytic_1e5x4"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
     st, y = gpu_yt(S, pr, None, "f64", c["seed"])
     ref = orc(pr, None, c["seed"], np.arange(c["N"]))
-    print("c0 f64 max rel", rel(y, ref).max())
+    print("analytic 1e5 x 4 f64 max rel", rel(y, ref).max())
     assert rel(y, ref).max() <= TOL["f64"]
     for k, f in enumerate(oracle.payoffs(ref, c["K"])):
         e = oracle.estimate(f)
@@ -73,13 +73,13 @@ def test_c0_f64_analytic_all_paths(S):
     assert st["n"] == c["N"]
 
 
-def test_c0_f32_analytic_all_paths(S):
-    c = W.CONFIGS["c0"]
+def test_gbm_analytic_1e5x4_f32_all_paths(S):
+    c = W.CONFIGS["gbm_analytic_1e5x4"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
     st, y = gpu_yt(S, pr, None, "f32", c["seed"])
     ref = orc(pr, None, c["seed"], np.arange(c["N"]))
     r = rel(y, ref)
-    print("c0 f32 max rel", r.max(), "p99", np.quantile(r, 0.99))
+    print("analytic 1e5 x 4 f32 max rel", r.max(), "p99", np.quantile(r, 0.99))
     assert r.max() <= TOL["f32"]
     for k, f in enumerate(oracle.payoffs(ref, c["K"])):
         e = oracle.estimate(f)
@@ -107,7 +107,7 @@ def test_analytic_every_m_and_ragged_M(S, m):
 
 @pytest.mark.parametrize("N", [1, 15, 63, 65, 1000, 4099])
 def test_ragged_path_counts(S, H, Ho, N):
-    c = W.CONFIGS["c1"]
+    c = W.CONFIGS["gbm_mlp_2p22x16"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 7, c["m"], N, K=c["K"])
     ref = orc(pr, Ho, 5, np.arange(N))
     for prec in ("f64", "f32", "bf16", "f16", "bf16x3", "f16x3"):
@@ -118,7 +118,7 @@ def test_ragged_path_counts(S, H, Ho, N):
 
 
 def test_mlp_f64_matches_oracle(S, H, Ho):
-    c = W.CONFIGS["c1"]
+    c = W.CONFIGS["gbm_mlp_2p22x16"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], 4096, K=c["K"])
     st, y = gpu_yt(S, pr, H, "f64", c["seed"])
     ref = orc(pr, Ho, c["seed"], np.arange(pr.N))
@@ -129,38 +129,38 @@ def test_mlp_f64_matches_oracle(S, H, Ho):
 
 
 def test_mlp_f32_paths_and_means(S, H, Ho):
-    """C1 setting on 2^17 paths: every path and both payoff means."""
-    c = W.CONFIGS["c1"]
+    """The 2^22 x 16 GBM setting on 2^17 paths: every path and both payoff means."""
+    c = W.CONFIGS["gbm_mlp_2p22x16"]
     N = 2 ** 17
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], N, K=c["K"])
     st, y = gpu_yt(S, pr, H, "f32", c["seed"])
     ref = orc(pr, Ho, c["seed"], np.arange(N))
     r = rel(y, ref)
-    print(f"f32 C1@2^17: max rel {r.max():.3e} p99 {np.quantile(r, 0.99):.3e}")
+    print(f"f32 GBM 16 steps, 2^17 paths: max rel {r.max():.3e} p99 {np.quantile(r, 0.99):.3e}")
     assert r.max() <= TOL["f32"]
     for k, f in enumerate(oracle.payoffs(ref, c["K"])):
         e = oracle.estimate(f)
         assert abs(st["mean"][k] - e["mean"]) <= 1e-6 * abs(e["mean"]), k
 
 
-def test_c1_full_size_sampled_paths(S, H, Ho):
+def test_gbm_2p22x16_full_size_sampled_paths(S, H, Ho):
     """N = 2^22, M = 16, the benchmark's default plan; the oracle recomputes
     the first and last 2^15 paths and a strided 2^16."""
-    c = W.CONFIGS["c1"]
+    c = W.CONFIGS["gbm_mlp_2p22x16"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
     st, y = gpu_yt(S, pr, H, "f32", c["seed"])
     sub = W.parity_subset(c["N"])
     ref = orc(pr, Ho, c["seed"], sub)
     r = rel(y[sub], ref)
-    print(f"f32 C1 full: max rel {r.max():.3e} over {len(sub)} paths")
+    print(f"f32 GBM 2^22 x 16 full: max rel {r.max():.3e} over {len(sub)} paths")
     assert r.max() <= TOL["f32"]
     assert st["n"] == c["N"]
     assert abs(st["mean"][0] - y.mean()) <= 1e-9 * abs(y.mean())
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "f16x3", "f32", "bf16", "f16"])
-def test_c2_full_size_sampled_paths(S, H, Ho, prec):
-    c = W.CONFIGS["c2"]
+def test_gbm_2p24x32_full_size_sampled_paths(S, H, Ho, prec):
+    c = W.CONFIGS["gbm_mlp_2p24x32"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
     st, y = gpu_yt(S, pr, H, prec, c["seed"])
     N = c["N"]
@@ -168,16 +168,16 @@ def test_c2_full_size_sampled_paths(S, H, Ho, prec):
                                     np.arange(0, N, N // 8192)]))
     ref = orc(pr, Ho, c["seed"], sub)
     r = rel(y[sub], ref)
-    print(f"{prec} C2 full: max rel {r.max():.3e} p99 {np.quantile(r, 0.99):.3e} over {len(sub)}")
+    print(f"{prec} GBM 2^24 x 32 full: max rel {r.max():.3e} p99 {np.quantile(r, 0.99):.3e} over {len(sub)}")
     assert r.max() <= TOL[prec]
 
 
-def test_c2_bf16x3_equal_weak_error_to_f32(S, H):
+def test_gbm_2p24x32_bf16x3_equal_weak_error_to_f32(S, H):
     """Same seed (common random numbers): the BF16x3 and FP32 means of Y_T
     differ by at most 2 SE of the paired difference or 10% of the FP32 weak
     error against the closed form E[Y_T] = Y0 exp(mu T)."""
     import math
-    c = W.CONFIGS["c2"]
+    c = W.CONFIGS["gbm_mlp_2p24x32"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
     st32, y32 = gpu_yt(S, pr, H, "f32", c["seed"])
     stb, yb = gpu_yt(S, pr, H, "bf16x3", c["seed"])
@@ -190,7 +190,7 @@ def test_c2_bf16x3_equal_weak_error_to_f32(S, H):
 
 
 def test_results_independent_of_launch_plan(S, H):
-    c = W.CONFIGS["c1"]
+    c = W.CONFIGS["gbm_mlp_2p22x16"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 9, c["m"], 50_001, K=c["K"])
     for prec in ("bf16", "f32", "bf16x3"):
         outs = []
@@ -205,7 +205,7 @@ def test_results_independent_of_launch_plan(S, H):
 
 
 def test_path_offset_shards_compose(S, H):
-    c = W.CONFIGS["c1"]
+    c = W.CONFIGS["gbm_mlp_2p22x16"]
     full = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 6, c["m"], 3000, K=c["K"])
     _, y = gpu_yt(S, full, H, "f32", 3)
     part = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 6, c["m"], 1000, K=c["K"],
@@ -234,7 +234,7 @@ def test_eval_H_matches_oracle_forward(S, H, Ho, prec):
 def test_degenerate_shapes(S, H, Ho, prec):
     """One step (M = 1), one path, a single 64-path block exactly, and the
     largest step of the training range, in every mode."""
-    c = W.CONFIGS["c1"]
+    c = W.CONFIGS["gbm_mlp_2p22x16"]
     tol = {"pwl32": TOL["f32"], "pwl64": TOL["f64"]}.get(prec, TOL.get(prec))
     for T, M, N in ((0.5, 1, 1), (0.5, 1, 64), (1.0, 2, 129), (0.05, 1, 777)):
         pr = S.Problem(c["model"], c["theta"], c["Y0"], T, M, c["m"], N, K=c["K"])

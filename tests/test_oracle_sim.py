@@ -22,12 +22,12 @@ import workloads as W
 
 
 def _c0_problem(orc):
-    c = W.CONFIGS["c0"]
+    c = W.CONFIGS["gbm_analytic_1e5x4"]
     return orc.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"])
 
 
-def test_c0_closed_form_mean_and_second_moment(orc):
-    c = W.CONFIGS["c0"]
+def test_gbm_analytic_closed_form_mean_and_second_moment(orc):
+    c = W.CONFIGS["gbm_analytic_1e5x4"]
     sig, mu = c["theta"]
     dt = c["T"] / c["M"]
     x, w = orc.gh_nodes(c["m"])

@@ -46,7 +46,7 @@ def probe_points(pw, lo, hi):
                            b - 1e-9 * np.maximum(1, abs(b)), [-1e6, 1e6]])
 
 
-@pytest.mark.parametrize("case", ["c1", "c2"])
+@pytest.mark.parametrize("case", ["gbm_mlp_2p22x16", "gbm_mlp_2p24x32"])
 def test_gbm_network_pieces_match_oracle(S, case):
     c = W.CONFIGS[case]
     H, Ho = S.Mlp.load(GBM_W), oracle.load_mlp(GBM_W)
@@ -74,7 +74,7 @@ def test_cir_network_pieces_match_oracle(S):
 
 
 def test_pieces_are_continuous(S):
-    c = W.CONFIGS["c2"]
+    c = W.CONFIGS["gbm_mlp_2p24x32"]
     pw = S.pwl_compile(S.Mlp.load(GBM_W), S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"],
                                                     c["m"], 100))
     b = pw["breaks"]
@@ -125,7 +125,7 @@ def test_piece_count_equals_brute_force_slope_changes(S):
 
 def test_limits_and_rejections(S):
     from paper_2302_05170_amd import _lib as L
-    c = W.CONFIGS["c2"]
+    c = W.CONFIGS["gbm_mlp_2p24x32"]
     H = S.Mlp.load(GBM_W)
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], 100)
     with pytest.raises(S.Sl7Error) as e:

@@ -8,15 +8,17 @@ drive the paths are not drawn here; each side derives them from its own
 counter-based generator.
 
 Workloads (synthetic; the paper uses no public dataset):
-  c0  GBM, analytic collocation map, FP64: mu 0.1, sigma 0.3, Y0 1, T 1,
-      M 4, m 5, N 1e5, seed 42.
-  c1  GBM, MLP map (4 inputs, 4x64 ReLU, 5 outputs), FP32: sigma 0.3,
-      mu 0.1, Y0 1, T 1, M 16, N 2^22, seed 42.
-  c2  same network, GEMMs in BF16 / FP16: sigma 0.4, mu 0.05, T 2, M 32,
-      N 2^24.
-  c3  adjoint of E[max(Y_T - 1, 0)] for the c1 setting, checkpoint every 4.
-  c4  256 CIR instances of uneven size (kappa, ybar, gamma, Y0, dt, M, N
-      drawn from seed 11), MLP with 5 inputs and 7 outputs, BF16.
+  gbm_analytic_1e5x4   GBM, analytic collocation map, FP64: mu 0.1,
+                       sigma 0.3, Y0 1, T 1, M 4, m 5, N 1e5, seed 42.
+  gbm_mlp_2p22x16      GBM, MLP map (4 inputs, 4x64 ReLU, 5 outputs), FP32:
+                       sigma 0.3, mu 0.1, Y0 1, T 1, M 16, N 2^22, seed 42.
+  gbm_mlp_2p24x32      same network, GEMMs in BF16 / FP16: sigma 0.4,
+                       mu 0.05, T 2, M 32, N 2^24.
+  gbm_adjoint_2p22x16  adjoint of E[max(Y_T - 1, 0)] in the 2^22 x 16
+                       setting, checkpoint every 4.
+  cir_instances(256)   256 CIR instances of uneven size (kappa, ybar, gamma,
+                       Y0, dt, M, N drawn from seed 11), MLP with 5 inputs and
+                       7 outputs, BF16.
 """
 from __future__ import annotations
 
@@ -27,13 +29,13 @@ GBM, OU, CIR = 0, 1, 2
 # GBM parameter vector order is (sigma, mu): the network's input order is
 # (Y, dt, sigma, mu).  OU: (ybar, sigma, lambda).  CIR: (kappa, ybar, gamma).
 CONFIGS = {
-    "c0": dict(model=GBM, theta=(0.3, 0.1), Y0=1.0, T=1.0, M=4, m=5, N=100_000,
+    "gbm_analytic_1e5x4": dict(model=GBM, theta=(0.3, 0.1), Y0=1.0, T=1.0, M=4, m=5, N=100_000,
                seed=42, K=1.0),
-    "c1": dict(model=GBM, theta=(0.3, 0.1), Y0=1.0, T=1.0, M=16, m=5, N=2 ** 22,
+    "gbm_mlp_2p22x16": dict(model=GBM, theta=(0.3, 0.1), Y0=1.0, T=1.0, M=16, m=5, N=2 ** 22,
                seed=42, K=1.0),
-    "c2": dict(model=GBM, theta=(0.4, 0.05), Y0=1.0, T=2.0, M=32, m=5, N=2 ** 24,
+    "gbm_mlp_2p24x32": dict(model=GBM, theta=(0.4, 0.05), Y0=1.0, T=2.0, M=32, m=5, N=2 ** 24,
                seed=42, K=1.0),
-    "c3": dict(model=GBM, theta=(0.3, 0.1), Y0=1.0, T=1.0, M=16, m=5, N=2 ** 22,
+    "gbm_adjoint_2p22x16": dict(model=GBM, theta=(0.3, 0.1), Y0=1.0, T=1.0, M=16, m=5, N=2 ** 22,
                seed=42, K=1.0, ckpt=4),
 }
 
@@ -93,7 +95,7 @@ def ou_features(n: int = N_LABELS, seed: int = TRAIN_SEED) -> np.ndarray:
 
 
 # The paper's OU experiment (Table 6.1) does not state T, M, theta or Y0;
-# these are this build's choice, with the paper's path counts.
+# these are chosen here, with the paper's path counts.
 OU_PAPER = dict(model=OU, theta=(0.5, 0.3, 1.0), Y0=0.2, T=2.0, M=8, m=5, seed=42, K=0.5,
                 path_counts=(1_000, 50_000, 100_000, 200_000))
 
