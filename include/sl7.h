@@ -48,7 +48,7 @@ extern "C" {
 /* Status codes. */
 #define SL7_OK 0
 #define SL7_EINVAL (-1)       /* an argument is out of range or inconsistent */
-#define SL7_EUNSUPPORTED (-2) /* valid request this build does not implement */
+#define SL7_EUNSUPPORTED (-2) /* valid request the library does not implement */
 #define SL7_EHIP (-3)         /* a HIP runtime call failed */
 #define SL7_ENOMEM (-4)       /* device or host allocation failed */
 #define SL7_ENUMERIC (-5)     /* non-finite weights or results */
@@ -227,7 +227,10 @@ typedef struct {
 } sl7_greeks;
 
 /* Workspace size (bytes) for sl7_adjoint: checkpoints
- * ceil(M / ckpt_every) x N states plus block sums. 0 for bad arguments. */
+ * ceil(M / ckpt_every) x N states, the evaluation state of one segment
+ * (ckpt_every x N x 32 bytes of ReLU masks in F64/F32, 4 bytes of piece
+ * index in the PWL modes; the analytic map needs none but the size does not
+ * depend on H) plus block sums.  0 for bad arguments. */
 size_t sl7_adjoint_ws_bytes(const sl7_problem* pr, int prec, int ckpt_every);
 
 /* H == NULL: analytic map (GBM, OU).  prec: SL7_F64 or SL7_F32 (the

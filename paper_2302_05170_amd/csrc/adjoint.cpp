@@ -6,6 +6,7 @@
 #include <cstring>
 #include <vector>
 
+#include "net_lane.hpp"
 #include "sl7_adjoint.hpp"
 #include "sl7_host.hpp"
 
@@ -16,16 +17,20 @@ namespace {
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
 struct WsLayout {
-  size_t ckpt, parts, result, total;
+  size_t ckpt, state, parts, result, total;
 };
 
+// Checkpoints, the per-step evaluation state of one segment (sized for the
+// network, which keeps the most), block partials, result.
 WsLayout layout_of(const sl7_problem* pr, int prec, int ckpt) {
   const size_t el = (prec == SL7_F64 || prec == SL7_PWL64) ? sizeof(double) : sizeof(float);
   const int64_t nseg = (pr->M + ckpt - 1) / ckpt;
   const int64_t nb = (pr->N + 63) / 64;
+  const int words = adjoint_state_words(is_pwl(prec) ? 2 : 1);
   WsLayout L;
   L.ckpt = 0;
-  L.parts = align256(el * (size_t)nseg * (size_t)pr->N);
+  L.state = align256(el * (size_t)nseg * (size_t)pr->N);
+  L.parts = L.state + align256(sizeof(uint32_t) * (size_t)words * (size_t)ckpt * 64 * (size_t)nb);
   L.result = L.parts + align256(sizeof(AdjPartial) * (size_t)nb);
   L.total = L.result + align256(sizeof(double) * 12);
   return L;
@@ -59,48 +64,61 @@ void analytic_derivs(const sl7_problem& pr, const double* x, AdjArgs& a) {
 
 }  // namespace
 
+namespace {
+
+// The network in the lane layout of the adjoint kernels (net_lane.hpp), in T.
+template <typename T>
+std::vector<T> lane_layout(const Mlp& H) {
+  std::vector<T> v(kLaneNetSize, T(0));
+  for (int o = 0; o < 64; ++o) v[o] = (T)((double)H.W(0, o, 0) * H.d.in_scale[0]);
+  for (int l = 0; l < 3; ++l) {
+    T* L = v.data() + kLaneWy + l * kLaneLayer;
+    for (int c = 0; c < 4; ++c)
+      for (int k = 0; k < 64; ++k)
+        for (int i = 0; i < 16; ++i) {
+          L[c * 1024 + 16 * k + i] = H.W(l + 1, 16 * c + i, k);         // forward
+          L[4096 + c * 1024 + 16 * k + i] = H.W(l + 1, k, 16 * c + i);  // reverse
+        }
+    for (int o = 0; o < 64; ++o) L[8192 + o] = H.b(l + 1, o);
+  }
+  T* Hd = v.data() + kLaneHead;
+  for (int j = 0; j < H.d.m; ++j) {
+    for (int k = 0; k < 64; ++k) Hd[64 * j + k] = H.W(4, j, k);
+    Hd[8 * 64 + j] = H.b(4, j);
+  }
+  return v;
+}
+
+template <typename T>
+int upload_lane(const Mlp& H, std::unique_ptr<DevBuf>& net, std::unique_ptr<DevBuf>& wth) {
+  const int nth = H.d.d_in - 2;
+  std::vector<double> wt((size_t)nth * 64);  // FP64 for both T
+  for (int k = 0; k < nth; ++k)
+    for (int o = 0; o < 64; ++o) wt[k * 64 + o] = (double)H.W(0, o, 2 + k) * H.d.in_scale[2 + k];
+  const std::vector<T> v = lane_layout<T>(H);
+  net.reset(new DevBuf());
+  wth.reset(new DevBuf());
+  int rc = net->reserve(v.size() * sizeof(T));
+  if (!rc) rc = wth->reserve(wt.size() * sizeof(double));
+  if (rc) { net.reset(); wth.reset(); return rc; }
+  hipError_t e = hipMemcpy(net->p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(wth->p, wt.data(), wt.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { net.reset(); wth.reset(); return hip_fail(e, "upload the adjoint's lane weights"); }
+  return SL7_OK;
+}
+
+}  // namespace
+
 namespace sl7 {
 
 // Lane layout of the network in T plus the first-layer weights of theta
 // (times their input scales), for the adjoint kernels.
 int Mlp::ensure_adjoint(int prec) {
-  int rc = ensure_device(SL7_F64);  // FP64 lane layout
+  int rc = ensure_device(SL7_F64);  // binds the handle to the current device
   if (rc) return rc;
   std::lock_guard<std::mutex> lk(mu);
-  const int nth = d.d_in - 2;
-  std::vector<double> wt((size_t)nth * 64);
-  for (int k = 0; k < nth; ++k)
-    for (int o = 0; o < 64; ++o) wt[k * 64 + o] = (double)W(0, o, 2 + k) * d.in_scale[2 + k];
-  if (prec == SL7_F64) {
-    if (wth64) return SL7_OK;
-    wth64.reset(new DevBuf());
-    rc = wth64->reserve(wt.size() * sizeof(double));
-    if (rc) return rc;
-    const hipError_t e = hipMemcpy(wth64->p, wt.data(), wt.size() * sizeof(double), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "upload theta weights");
-    return SL7_OK;
-  }
-  if (net32 && wth32) return SL7_OK;
-  std::vector<float> v;
-  for (int o = 0; o < 64; ++o) v.push_back((float)((double)W(0, o, 0) * d.in_scale[0]));
-  for (int l = 1; l <= 3; ++l) {
-    for (int o = 0; o < 64; ++o)
-      for (int k = 0; k < 64; ++k) v.push_back(W(l, o, k));
-    for (int o = 0; o < 64; ++o) v.push_back(b(l, o));
-  }
-  for (int j = 0; j < d.m; ++j)
-    for (int k = 0; k < 64; ++k) v.push_back(W(4, j, k));
-  for (int j = 0; j < d.m; ++j) v.push_back(b(4, j));
-  std::vector<float> wt32(wt.begin(), wt.end());
-  net32.reset(new DevBuf());
-  wth32.reset(new DevBuf());
-  rc = net32->reserve(v.size() * sizeof(float));
-  if (!rc) rc = wth32->reserve(wt32.size() * sizeof(float));
-  if (rc) return rc;
-  hipError_t e = hipMemcpy(net32->p, v.data(), v.size() * sizeof(float), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(wth32->p, wt32.data(), wt32.size() * sizeof(float), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "upload FP32 lane weights");
-  return SL7_OK;
+  if (prec == SL7_F64) return adj64 && wth64 ? SL7_OK : upload_lane<double>(*this, adj64, wth64);
+  return adj32 && wth32 ? SL7_OK : upload_lane<float>(*this, adj32, wth32);
 }
 
 }  // namespace sl7
@@ -160,12 +178,13 @@ extern "C" int sl7_adjoint(const sl7_problem* pr, const sl7_mlp* Hc, int prec, u
     a.net = sa.wpack;  // the piecewise-linear tables with theta derivatives
   } else if (H) {
     mode = 1;
-    a.net = prec == SL7_F64 ? H->net64->p : H->net32->p;
+    a.net = prec == SL7_F64 ? H->adj64->p : H->adj32->p;
     a.wtheta = prec == SL7_F64 ? H->wth64->p : H->wth32->p;
     a.c0 = instp + (prec == SL7_F64 ? offsetof(InstDev, c0d) : offsetof(InstDev, c0));
   }
   char* w = (char*)ws_dev;
   a.ckpt_buf = w + Lw.ckpt;
+  a.state_buf = (uint32_t*)(w + Lw.state);
   a.partials = (AdjPartial*)(w + Lw.parts);
   a.result = (double*)(w + Lw.result);
   a.per_path = per_path_dev;

@@ -246,7 +246,8 @@ float Mlp::b(int l, int o) const {
 void Mlp::drop_device() {
   for (auto& p : pack) p.reset();
   net64.reset();
-  net32.reset();
+  adj64.reset();
+  adj32.reset();
   wth64.reset();
   wth32.reset();
   w0full.reset();

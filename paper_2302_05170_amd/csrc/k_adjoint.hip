@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
+#include "net_lane.hpp"
 #include "pwl_device.hpp"
 #include "sl7_adjoint.hpp"
 
@@ -38,8 +39,8 @@ constexpr int kAdjAnalytic = 0, kAdjNet = 1, kAdjPwl = 2;
 // layers are returned in mask[l*2 + (unit/32)] bit (unit%32); for the
 // piecewise-linear form mask[0] holds the piece index.
 template <typename T, int MODE>
-__device__ __forceinline__ void colloc(const AdjArgs& a, const InstDev& I, T Y, T* hA, T* hB,
-                                       T y[kMaxM], uint32_t mask[8]) {
+__device__ __forceinline__ void colloc(const AdjArgs& a, const InstDev& I, T Y, T* stage,
+                                       T (&y)[kMaxM], uint32_t (&mask)[8]) {
   const int m = a.m;
   if constexpr (MODE == kAdjPwl) {
     const char* base = (const char*)a.net;
@@ -50,40 +51,10 @@ __device__ __forceinline__ void colloc(const AdjArgs& a, const InstDev& I, T Y, 
 #pragma unroll
     for (int j = 0; j < kMaxM; ++j) y[j] = j < m ? fma(rec[j], dY, rec[kMaxM + j]) : T(0);
   } else if constexpr (MODE == kAdjNet) {
-    const T* W = (const T*)a.net;
-    const T* c0 = (const T*)a.c0;
-    for (int q = 0; q < 8; ++q) mask[q] = 0u;
-    for (int o = 0; o < 64; ++o) {
-      const T z = fma(W[o], Y, c0[o]);
-      if (z > T(0)) mask[o >> 5] |= 1u << (o & 31);
-      hA[o * 64] = z > T(0) ? z : T(0);
-    }
-    const T* Wl = W + 64;
-    T* hin = hA;
-    T* hout = hB;
-    for (int l = 1; l < 4; ++l) {
-      const T* bl = Wl + 64 * 64;
-      for (int o = 0; o < 64; ++o) {
-        T s = bl[o];
-        const T* row = Wl + o * 64;
-#pragma unroll 8
-        for (int k = 0; k < 64; ++k) s = fma(row[k], hin[k * 64], s);
-        if (s > T(0)) mask[2 * l + (o >> 5)] |= 1u << (o & 31);
-        hout[o * 64] = s > T(0) ? s : T(0);
-      }
-      Wl += 64 * 64 + 64;
-      T* t = hin; hin = hout; hout = t;
-    }
-    const T* bh = Wl + 64 * m;
+    LaneMasks mk;
+    lane_net_fwd<T, kMaxM>(a.net, a.c0, m, Y, y, mk, stage);
 #pragma unroll
-    for (int j = 0; j < kMaxM; ++j) {
-      if (j < m) {
-        T s = bh[j];
-        const T* row = Wl + j * 64;
-        for (int k = 0; k < 64; ++k) s = fma(row[k], hin[k * 64], s);
-        y[j] = s;
-      }
-    }
+    for (int q = 0; q < 8; ++q) mask[q] = mk.w[q];
   } else {
 #pragma unroll
     for (int j = 0; j < kMaxM; ++j) y[j] = (T)I.A[j] * Y + (T)I.B[j];
@@ -91,9 +62,9 @@ __device__ __forceinline__ void colloc(const AdjArgs& a, const InstDev& I, T Y, 
 }
 
 // Lagrange basis at X (second barycentric form; a node hit gives a unit
-// vector) and the interpolated value.
+// vector).
 template <typename T>
-__device__ __forceinline__ T basis(const AdjArgs& a, T X, const T y[kMaxM], T L[kMaxM]) {
+__device__ __forceinline__ void basis(const AdjArgs& a, T X, T (&L)[kMaxM]) {
   const int m = a.m;
   int hit = -1;
   T den = T(0);
@@ -108,22 +79,27 @@ __device__ __forceinline__ T basis(const AdjArgs& a, T X, const T y[kMaxM], T L[
       den += L[j];
     }
   }
+#pragma unroll
+  for (int j = 0; j < kMaxM; ++j)
+    if (j < m) L[j] = hit >= 0 ? (j == hit ? T(1) : T(0)) : L[j] / den;
+}
+
+// g_m(X) = sum_j L_j(X) y_j.
+template <typename T>
+__device__ __forceinline__ T interpolate(const AdjArgs& a, const T (&L)[kMaxM],
+                                         const T (&y)[kMaxM]) {
   T g = T(0);
 #pragma unroll
-  for (int j = 0; j < kMaxM; ++j) {
-    if (j < m) {
-      L[j] = hit >= 0 ? (j == hit ? T(1) : T(0)) : L[j] / den;
-      g += L[j] * y[j];
-    }
-  }
+  for (int j = 0; j < kMaxM; ++j)
+    if (j < a.m) g += L[j] * y[j];
   return g;
 }
 
 // Vector-Jacobian product of the collocation map: given ybar, returns
 // dY = ybar . dy/dY and adds ybar . dy/dtheta_k into thb[k].
 template <typename T, int MODE>
-__device__ __forceinline__ T vjp(const AdjArgs& a, const InstDev& I, T Y, const T ybar[kMaxM],
-                                 const uint32_t mask[8], T* dA, T* dB, double thb[4]) {
+__device__ __forceinline__ T vjp(const AdjArgs& a, const InstDev& I, T Y, const T (&ybar)[kMaxM],
+                                 const uint32_t (&mask)[8], T* stage, double (&thb)[4]) {
   const int m = a.m;
   const int nth = a.n_theta;
   if constexpr (MODE == kAdjPwl) {
@@ -143,39 +119,10 @@ __device__ __forceinline__ T vjp(const AdjArgs& a, const InstDev& I, T Y, const 
     }
     return dY;
   } else if constexpr (MODE == kAdjNet) {
-    const T* W = (const T*)a.net;
-    const T* Wh = W + 64 + 3 * (64 * 64 + 64);
-    // cotangent of the last hidden layer
-    for (int k = 0; k < 64; ++k) {
-      T g = T(0);
+    LaneMasks mk;
 #pragma unroll
-      for (int j = 0; j < kMaxM; ++j)
-        if (j < m) g = fma(Wh[j * 64 + k], ybar[j], g);
-      dA[k * 64] = ((mask[6 + (k >> 5)] >> (k & 31)) & 1u) ? g : T(0);
-    }
-    T* dn = dA;
-    T* dp = dB;
-    for (int l = 3; l >= 1; --l) {
-      const T* Wl = W + 64 + (l - 1) * (64 * 64 + 64);
-      for (int k = 0; k < 64; ++k) {
-        T g = T(0);
-#pragma unroll 8
-        for (int o = 0; o < 64; ++o) g = fma(Wl[o * 64 + k], dn[o * 64], g);
-        dp[k * 64] = ((mask[2 * (l - 1) + (k >> 5)] >> (k & 31)) & 1u) ? g : T(0);
-      }
-      T* t = dn; dn = dp; dp = t;
-    }
-    // dn: cotangent of the first hidden layer's pre-activation
-    const T* wT = (const T*)a.wtheta;
-    T dY = T(0);
-    double acc[4] = {0, 0, 0, 0};
-    for (int o = 0; o < 64; ++o) {
-      const T d = dn[o * 64];
-      dY = fma(W[o], d, dY);
-      for (int k = 0; k < nth; ++k) acc[k] += (double)(wT[k * 64 + o] * d);
-    }
-    for (int k = 0; k < nth; ++k) thb[k] += acc[k];
-    return dY;
+    for (int q = 0; q < 8; ++q) mk.w[q] = mask[q];
+    return lane_net_vjp<T, kMaxM>(a.net, a.wtheta, m, nth, ybar, mk, thb, stage);
   } else {
     T dY = T(0);
 #pragma unroll
@@ -192,59 +139,90 @@ __device__ __forceinline__ T vjp(const AdjArgs& a, const InstDev& I, T Y, const 
   }
 }
 
+// Words of evaluation state kept per step for the reverse sweep: the ReLU
+// masks of the network, the piece index of the piecewise-linear form.
+template <int MODE>
+constexpr int state_words() { return MODE == kAdjNet ? 8 : (MODE == kAdjPwl ? 1 : 0); }
+
+// The sweep visits every step three times: the forward pass (Y_T and the
+// checkpoints), the recomputation of its segment from the checkpoint (the
+// states Y_i, the evaluation state and the clamp flags, kept for the
+// segment), and the reverse step, which needs no evaluation of the map.
+// Forward pass and recomputation share one loop, so each evaluation routine
+// appears once in the code.
+// Waves per SIMD the register allocation aims at: the network sweep keeps a
+// 64-entry activation vector per lane (two per SIMD in FP64, three in FP32).
 template <typename T, int MODE>
-__global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
+constexpr int adjoint_waves() { return MODE != kAdjNet ? 1 : (sizeof(T) == 8 ? 2 : 3); }
+
+template <typename T, int MODE>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, 64),
+                          amdgpu_waves_per_eu(adjoint_waves<T, MODE>()))) void k_adjoint(AdjArgs a) {
   extern __shared__ double lds_adj[];
+  constexpr int NW = state_words<MODE>();
   const InstDev& I = a.inst[0];
   const int lane = threadIdx.x;
-  // network activations (MODE kAdjNet only), then the segment's states
-  T* hA = (T*)lds_adj + lane;
-  T* hB = hA + 64 * 64;
-  T* ybuf = (MODE == kAdjNet ? hB + 64 * 64 : (T*)lds_adj + lane);  // [ckpt][64]
+  const int k = a.ckpt;
+  // LDS: the network's per-lane output column (MODE kAdjNet only), then the
+  // segment's states [ckpt][64] and clamp flags [ckpt][64]
+  T* stage = (T*)lds_adj + lane;
+  T* ybuf = (T*)lds_adj + (MODE == kAdjNet ? kLaneStageRows * 64 : 0) + lane;
+  uint32_t* cbuf = (uint32_t*)(ybuf - lane + k * 64) + lane;
+  // evaluation state of the segment's steps, [ckpt][NW][64] per block
+  uint32_t* st = a.state_buf + (int64_t)blockIdx.x * k * NW * 64 + lane;
   const int64_t p = (int64_t)blockIdx.x * 64 + lane;
   const bool valid = p < I.N;
   const int64_t gp = I.path_offset + p;
   const uint32_t tag = (uint32_t)I.tag;
-  const int M = I.M, k = a.ckpt;
+  const int M = I.M;
   const bool clamp = I.clamp_zero != 0;
   T* ck = (T*)a.ckpt_buf;
   T y[kMaxM], L[kMaxM], ybar[kMaxM];
   uint32_t mask[8];
-  // forward with checkpoints
-  T Y = sizeof(T) == 8 ? (T)I.Y0 : (T)I.Y0_f;
-  for (int i = 0; i < M; ++i) {
-    if (i % k == 0 && valid) ck[(int64_t)(i / k) * I.N + p] = Y;
-    const T X = step_normal<T>(a, i, gp, tag);
-    colloc<T, MODE>(a, I, Y, hA, hB, y, mask);
-    Y = basis<T>(a, X, y, L);
-    if (clamp && Y < T(0)) Y = T(0);
-  }
   const T K = sizeof(T) == 8 ? (T)I.K : (T)I.K_f;
-  const double f = a.payoff == 0 ? (double)Y : fmax((double)Y - (double)K, 0.0);
-  T lam = a.payoff == 0 ? T(1) : (Y > K ? T(1) : T(0));
+  double f = 0.0;
+  T lam = T(0);
   double thb[4] = {0, 0, 0, 0};
   const int nseg = (M + k - 1) / k;
-  for (int seg = nseg - 1; seg >= 0; --seg) {
-    const int i0 = seg * k, i1 = min(i0 + k, M);
-    T Yc = valid ? ck[(int64_t)seg * I.N + p] : (T)I.Y0;
-    for (int i = i0; i < i1; ++i) {
-      ybuf[(i - i0) * 64] = Yc;
-      if (i + 1 < i1) {
-        const T X = step_normal<T>(a, i, gp, tag);
-        colloc<T, MODE>(a, I, Yc, hA, hB, y, mask);
-        Yc = basis<T>(a, X, y, L);
-        if (clamp && Yc < T(0)) Yc = T(0);
+  for (int pass = 0; pass <= nseg; ++pass) {
+    const bool fwd = pass == 0;
+    const int seg = nseg - pass;
+    const int ib = fwd ? 0 : seg * k;
+    const int ie = fwd ? M : min(ib + k, M);
+    T Yc = (fwd || !valid) ? (sizeof(T) == 8 ? (T)I.Y0 : (T)I.Y0_f) : ck[(int64_t)seg * I.N + p];
+    for (int i = ib; i < ie; ++i) {
+      if (fwd) {
+        if (i % k == 0 && valid) ck[(int64_t)(i / k) * I.N + p] = Yc;
+      } else {
+        ybuf[(i - ib) * 64] = Yc;
+      }
+      const T X = step_normal<T>(a, i, gp, tag);
+      colloc<T, MODE>(a, I, Yc, stage, y, mask);
+      basis<T>(a, X, L);
+      Yc = interpolate<T>(a, L, y);
+      const bool cl = clamp && Yc < T(0);
+      if (cl) Yc = T(0);
+      if (!fwd) {
+        cbuf[(i - ib) * 64] = cl ? 1u : 0u;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) st[((i - ib) * NW + q) * 64] = mask[q];
       }
     }
-    for (int i = i1 - 1; i >= i0; --i) {
-      const T Yi = ybuf[(i - i0) * 64];
+    if (fwd) {
+      f = a.payoff == 0 ? (double)Yc : fmax((double)Yc - (double)K, 0.0);
+      lam = a.payoff == 0 ? T(1) : (Yc > K ? T(1) : T(0));
+      continue;
+    }
+    for (int i = ie - 1; i >= ib; --i) {
+      const T Yi = ybuf[(i - ib) * 64];
       const T X = step_normal<T>(a, i, gp, tag);
-      colloc<T, MODE>(a, I, Yi, hA, hB, y, mask);
-      const T g = basis<T>(a, X, y, L);
-      const bool pass = !(clamp && g < T(0));
+      basis<T>(a, X, L);
+      const bool through = cbuf[(i - ib) * 64] == 0u;
 #pragma unroll
-      for (int j = 0; j < kMaxM; ++j) ybar[j] = pass ? lam * L[j] : T(0);
-      lam = vjp<T, MODE>(a, I, Yi, ybar, mask, hA, hB, thb);
+      for (int j = 0; j < kMaxM; ++j) ybar[j] = through ? lam * L[j] : T(0);
+#pragma unroll
+      for (int q = 0; q < NW; ++q) mask[q] = st[((i - ib) * NW + q) * 64];
+      lam = vjp<T, MODE>(a, I, Yi, ybar, mask, stage, thb);
     }
   }
   // per-path outputs: f, dY0, dtheta
@@ -310,7 +288,13 @@ __global__ __launch_bounds__(256) void k_adjoint_finalize(const AdjPartial* __re
 
 size_t adjoint_lds_bytes(int prec, int mode, int ckpt) {
   const size_t el = (prec == SL7_F64 || prec == SL7_PWL64) ? sizeof(double) : sizeof(float);
-  return el * ((mode == kAdjNet ? 2 * 64 * 64 : 0) + (size_t)ckpt * 64);
+  return el * ((mode == kAdjNet ? kLaneStageRows * 64 : 0) + (size_t)ckpt * 64) +
+         sizeof(uint32_t) * (size_t)ckpt * 64;
+}
+
+int adjoint_state_words(int mode) {
+  return mode == kAdjNet ? state_words<kAdjNet>()
+                         : (mode == kAdjPwl ? state_words<kAdjPwl>() : state_words<kAdjAnalytic>());
 }
 
 template <typename T, int MODE>

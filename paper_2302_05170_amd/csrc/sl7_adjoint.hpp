@@ -15,8 +15,9 @@ struct AdjArgs {
   int32_t m, n_theta, ckpt, payoff;
   const void* net;     // lane layout of the network (T), the piecewise-linear tables, or NULL
   const void* c0;      // first-layer constant of the instance (T, device)
-  const void* wtheta;  // [n_theta x 64] first-layer weight of theta_k times its scale (T)
+  const void* wtheta;  // [n_theta x 64] first-layer weight of theta_k times its scale (double)
   void* ckpt_buf;      // [ceil(M/ckpt) x N] states (T)
+  uint32_t* state_buf; // [blocks][ckpt][words][64]: per-step evaluation state of a segment
   AdjPartial* partials;
   double* result;      // [12]: means then standard errors
   double* per_path;    // NULL or [N x (2 + n_theta)]
@@ -29,6 +30,9 @@ struct AdjArgs {
 // mode: 0 analytic map, 1 network (lane back-propagation), 2 piecewise-
 // linear form (a.net = table base).  prec F64 / PWL64 run in double.
 size_t adjoint_lds_bytes(int prec, int mode, int ckpt);
+// 32-bit words of evaluation state kept per path and step (8 network, 1
+// piecewise-linear, 0 analytic).
+int adjoint_state_words(int mode);
 hipError_t launch_adjoint(int prec, int mode, const AdjArgs& a, int64_t n_blocks, hipStream_t s);
 
 }  // namespace sl7

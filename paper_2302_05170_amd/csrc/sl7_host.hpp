@@ -81,7 +81,7 @@ struct Mlp {
   int device = -1;
   std::unique_ptr<DevBuf> pack[6];  // MFMA register layouts, by precision
   std::unique_ptr<DevBuf> net64, w0full, w0n, c0n;
-  std::unique_ptr<DevBuf> net32, wth64, wth32;  // adjoint lane layouts
+  std::unique_ptr<DevBuf> adj64, adj32, wth64, wth32;  // adjoint lane layouts
   // compiled piecewise-linear forms by instance (model, dt, theta); cleared
   // with the device copies whenever the parameters change
   std::map<std::array<double, 5>, std::shared_ptr<PwlPieces>> pwl_cache;
