@@ -234,8 +234,11 @@ typedef struct {
 size_t sl7_adjoint_ws_bytes(const sl7_problem* pr, int prec, int ckpt_every);
 
 /* H == NULL: analytic map (GBM, OU).  prec: SL7_F64 or SL7_F32 (the
- * accumulation of the theta-gradients is FP64 in both); for a ReLU network
- * also SL7_PWL64 / SL7_PWL32, which back-propagate through the network's
+ * accumulation of the theta-gradients is FP64 in both), with the analytic
+ * map, a ReLU network or a Softplus network (whose reverse pass recomputes
+ * each hidden layer's pre-activation from Y_i for the logistic derivative);
+ * for a ReLU network also SL7_PWL64 / SL7_PWL32, which back-propagate
+ * through the network's
  * piecewise-linear form: per piece the slope in Y and dy_j/dtheta_k (the
  * piece's activation pattern held fixed, as back-propagation holds its ReLU
  * masks) are compiled on the host in FP64 with the pieces.  ws_dev: caller's

@@ -91,6 +91,7 @@ std::vector<T> lane_layout(const Mlp& H) {
 
 template <typename T>
 int upload_lane(const Mlp& H, std::unique_ptr<DevBuf>& net, std::unique_ptr<DevBuf>& wth) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "FP32 or FP64");
   const int nth = H.d.d_in - 2;
   std::vector<double> wt((size_t)nth * 64);  // FP64 for both T
   for (int k = 0; k < nth; ++k)
@@ -111,14 +112,18 @@ int upload_lane(const Mlp& H, std::unique_ptr<DevBuf>& net, std::unique_ptr<DevB
 
 namespace sl7 {
 
-// Lane layout of the network in T plus the first-layer weights of theta
-// (times their input scales), for the adjoint kernels.
+int upload_lane_layout(const Mlp& H, int prec, std::unique_ptr<DevBuf>& net,
+                       std::unique_ptr<DevBuf>& wth) {
+  return prec == SL7_F64 ? upload_lane<double>(H, net, wth) : upload_lane<float>(H, net, wth);
+}
+
+// Lane layout of the network in the sweep's precision plus the first-layer
+// weights of theta (times their input scales), for the adjoint kernels.
 int Mlp::ensure_adjoint(int prec) {
-  int rc = ensure_device(SL7_F64);  // binds the handle to the current device
-  if (rc) return rc;
+  int rc = ensure_device(SL7_F64);  // binds the handle to the device; builds the FP64 layout
+  if (rc || prec == SL7_F64) return rc;
   std::lock_guard<std::mutex> lk(mu);
-  if (prec == SL7_F64) return adj64 && wth64 ? SL7_OK : upload_lane<double>(*this, adj64, wth64);
-  return adj32 && wth32 ? SL7_OK : upload_lane<float>(*this, adj32, wth32);
+  return lane32 && wth32 ? SL7_OK : upload_lane<float>(*this, lane32, wth32);
 }
 
 }  // namespace sl7
@@ -140,7 +145,6 @@ extern "C" int sl7_adjoint(const sl7_problem* pr, const sl7_mlp* Hc, int prec, u
   if (ckpt_every < 1 || ckpt_every > 32) return fail(SL7_EINVAL, "ckpt_every=%d outside [1, 32]", ckpt_every);
   if (!out) return fail(SL7_EINVAL, "out is NULL");
   if (!ws_dev) return fail(SL7_EINVAL, "ws_dev is NULL");
-  if (H && H->d.act != SL7_RELU) return fail(SL7_EUNSUPPORTED, "the adjoint back-propagates ReLU networks only");
   const WsLayout Lw = layout_of(pr, prec, ckpt_every);
   if (ws_bytes < Lw.total) return fail(SL7_EINVAL, "ws_bytes=%zu < %zu needed", ws_bytes, Lw.total);
   if (H && !is_pwl(prec)) {
@@ -177,8 +181,8 @@ extern "C" int sl7_adjoint(const sl7_problem* pr, const sl7_mlp* Hc, int prec, u
     mode = 2;
     a.net = sa.wpack;  // the piecewise-linear tables with theta derivatives
   } else if (H) {
-    mode = 1;
-    a.net = prec == SL7_F64 ? H->adj64->p : H->adj32->p;
+    mode = H->d.act == SL7_RELU ? 1 : 3;
+    a.net = prec == SL7_F64 ? H->lane64->p : H->lane32->p;
     a.wtheta = prec == SL7_F64 ? H->wth64->p : H->wth32->p;
     a.c0 = instp + (prec == SL7_F64 ? offsetof(InstDev, c0d) : offsetof(InstDev, c0));
   }

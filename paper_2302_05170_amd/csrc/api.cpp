@@ -246,8 +246,8 @@ float Mlp::b(int l, int o) const {
 void Mlp::drop_device() {
   for (auto& p : pack) p.reset();
   net64.reset();
-  adj64.reset();
-  adj32.reset();
+  lane64.reset();
+  lane32.reset();
   wth64.reset();
   wth32.reset();
   w0full.reset();
@@ -391,6 +391,11 @@ int Mlp::ensure_device(int prec) {
   }
   if (is_pwl(prec)) return SL7_OK;  // tables are built per call (prepare_instances)
   if (prec == SL7_F64) {
+    if (net64 && lane64) return SL7_OK;
+    if (!lane64) {
+      rc = upload_lane_layout(*this, SL7_F64, lane64, wth64);
+      if (rc) return rc;
+    }
     if (net64) return SL7_OK;
     const int m = d.m;
     std::vector<double> v;
@@ -675,7 +680,7 @@ int launch_instances(const SimArgs& a_in, int n, int64_t N0, const Mlp* H, int p
     if (e != hipSuccess) return hip_fail(e, "launch fused MFMA kernel");
   } else {
     if (n != 1) return fail(SL7_EUNSUPPORTED, "batched launches need a network in F32/BF16/F16");
-    a.wpack = H ? H->net64->p : nullptr;
+    a.wpack = H ? H->lane64->p : nullptr;
     e = launch_sim_lane(prec, H ? 1 : 0, H ? H->d.act : 0, a, (N0 + 63) / 64, stream);
     if (e != hipSuccess) return hip_fail(e, "launch per-lane kernel");
   }

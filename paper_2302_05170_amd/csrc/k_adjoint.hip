@@ -8,10 +8,11 @@
 //   ybar_j = lambda * L_j(X)                 (L_j the Lagrange basis at X)
 //   lambda <- sum_j ybar_j dy_j/dY,  thetabar += sum_j ybar_j dy_j/dtheta
 // where dy/d(Y, theta) comes from the analytic map, from back-propagation
-// through the network (eq. 6.3/6.4; ReLU masks kept in registers) or, for a
-// ReLU network in its piecewise-linear form, from the piece's record (slope
-// in Y and the theta derivatives compiled on the host).  Starts
-// from lambda = f'(Y_T); a CIR step clamped to 0 passes no gradient.
+// through the network (eq. 6.3/6.4; ReLU masks kept from the recomputation,
+// Softplus derivatives recomputed from Y) or, for a ReLU network in its
+// piecewise-linear form, from the piece's record (slope in Y and the theta
+// derivatives compiled on the host).  Starts from lambda = f'(Y_T); a CIR
+// step clamped to 0 passes no gradient.
 // thetabar accumulates in FP64.  One path per lane, one 64-path block per
 // workgroup; block sums in a fixed order.
 #include <hip/hip_runtime.h>
@@ -33,7 +34,8 @@ __device__ __forceinline__ T step_normal(const AdjArgs& a, int i, int64_t gp, ui
 }
 
 // Map evaluation modes of the adjoint.
-constexpr int kAdjAnalytic = 0, kAdjNet = 1, kAdjPwl = 2;
+constexpr int kAdjAnalytic = 0, kAdjNet = 1, kAdjPwl = 2, kAdjNetSoftplus = 3;
+constexpr bool is_net(int mode) { return mode == kAdjNet || mode == kAdjNetSoftplus; }
 
 // Collocation points at Y; for the network the ReLU masks of the four hidden
 // layers are returned in mask[l*2 + (unit/32)] bit (unit%32); for the
@@ -50,9 +52,10 @@ __device__ __forceinline__ void colloc(const AdjArgs& a, const InstDev& I, T Y, 
     const T dY = Y - rec[2 * kMaxM];
 #pragma unroll
     for (int j = 0; j < kMaxM; ++j) y[j] = j < m ? fma(rec[j], dY, rec[kMaxM + j]) : T(0);
-  } else if constexpr (MODE == kAdjNet) {
+  } else if constexpr (is_net(MODE)) {
     LaneMasks mk;
-    lane_net_fwd<T, kMaxM>(a.net, a.c0, m, Y, y, mk, stage);
+    lane_net_fwd<T, kMaxM, MODE == kAdjNet ? SL7_RELU : SL7_SOFTPLUS>(a.net, a.c0, m, Y, y, mk,
+                                                                       stage);
 #pragma unroll
     for (int q = 0; q < 8; ++q) mask[q] = mk.w[q];
   } else {
@@ -123,6 +126,8 @@ __device__ __forceinline__ T vjp(const AdjArgs& a, const InstDev& I, T Y, const 
 #pragma unroll
     for (int q = 0; q < 8; ++q) mk.w[q] = mask[q];
     return lane_net_vjp<T, kMaxM>(a.net, a.wtheta, m, nth, ybar, mk, thb, stage);
+  } else if constexpr (MODE == kAdjNetSoftplus) {
+    return lane_net_vjp_softplus<T, kMaxM>(a.net, a.c0, a.wtheta, m, nth, Y, ybar, thb, stage);
   } else {
     T dY = T(0);
 #pragma unroll
@@ -150,10 +155,16 @@ constexpr int state_words() { return MODE == kAdjNet ? 8 : (MODE == kAdjPwl ? 1 
 // segment), and the reverse step, which needs no evaluation of the map.
 // Forward pass and recomputation share one loop, so each evaluation routine
 // appears once in the code.
-// Waves per SIMD the register allocation aims at: the network sweep keeps a
-// 64-entry activation vector per lane (two per SIMD in FP64, three in FP32).
+// Waves per SIMD the register allocation aims at.  The network sweep keeps
+// a 64-entry activation vector per lane; measured fastest: three waves per
+// SIMD in FP32 and two in FP64 (one wave alone cannot keep the FP64 FMA
+// pipe busy, even with no spills), and one fewer for Softplus, which also
+// keeps the cotangent vector.
 template <typename T, int MODE>
-constexpr int adjoint_waves() { return MODE != kAdjNet ? 1 : (sizeof(T) == 8 ? 2 : 3); }
+constexpr int adjoint_waves() {
+  return MODE == kAdjNet ? (sizeof(T) == 8 ? 2 : 3)
+                         : (MODE == kAdjNetSoftplus ? (sizeof(T) == 8 ? 1 : 2) : 1);
+}
 
 template <typename T, int MODE>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, 64),
@@ -163,10 +174,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, 64),
   const InstDev& I = a.inst[0];
   const int lane = threadIdx.x;
   const int k = a.ckpt;
-  // LDS: the network's per-lane output column (MODE kAdjNet only), then the
+  // LDS: the network's per-lane output column (network modes only), then the
   // segment's states [ckpt][64] and clamp flags [ckpt][64]
   T* stage = (T*)lds_adj + lane;
-  T* ybuf = (T*)lds_adj + (MODE == kAdjNet ? kLaneStageRows * 64 : 0) + lane;
+  T* ybuf = (T*)lds_adj + (is_net(MODE) ? kLaneStageRows * 64 : 0) + lane;
   uint32_t* cbuf = (uint32_t*)(ybuf - lane + k * 64) + lane;
   // evaluation state of the segment's steps, [ckpt][NW][64] per block
   uint32_t* st = a.state_buf + (int64_t)blockIdx.x * k * NW * 64 + lane;
@@ -288,13 +299,15 @@ __global__ __launch_bounds__(256) void k_adjoint_finalize(const AdjPartial* __re
 
 size_t adjoint_lds_bytes(int prec, int mode, int ckpt) {
   const size_t el = (prec == SL7_F64 || prec == SL7_PWL64) ? sizeof(double) : sizeof(float);
-  return el * ((mode == kAdjNet ? kLaneStageRows * 64 : 0) + (size_t)ckpt * 64) +
+  return el * ((is_net(mode) ? kLaneStageRows * 64 : 0) + (size_t)ckpt * 64) +
          sizeof(uint32_t) * (size_t)ckpt * 64;
 }
 
 int adjoint_state_words(int mode) {
   return mode == kAdjNet ? state_words<kAdjNet>()
-                         : (mode == kAdjPwl ? state_words<kAdjPwl>() : state_words<kAdjAnalytic>());
+         : mode == kAdjPwl ? state_words<kAdjPwl>()
+         : mode == kAdjNetSoftplus ? state_words<kAdjNetSoftplus>()
+                                   : state_words<kAdjAnalytic>();
 }
 
 template <typename T, int MODE>
@@ -311,13 +324,15 @@ hipError_t launch_adjoint(int prec, int mode, const AdjArgs& a, int64_t n_blocks
   const bool f64 = prec == SL7_F64 || prec == SL7_PWL64;
   hipError_t e;
   if (f64) {
-    e = mode == kAdjNet ? launch_one<double, kAdjNet>(a, n_blocks, lds, s)
-        : mode == kAdjPwl ? launch_one<double, kAdjPwl>(a, n_blocks, lds, s)
-                          : launch_one<double, kAdjAnalytic>(a, n_blocks, lds, s);
+    e = mode == kAdjNet           ? launch_one<double, kAdjNet>(a, n_blocks, lds, s)
+        : mode == kAdjNetSoftplus ? launch_one<double, kAdjNetSoftplus>(a, n_blocks, lds, s)
+        : mode == kAdjPwl         ? launch_one<double, kAdjPwl>(a, n_blocks, lds, s)
+                                  : launch_one<double, kAdjAnalytic>(a, n_blocks, lds, s);
   } else {
-    e = mode == kAdjNet ? launch_one<float, kAdjNet>(a, n_blocks, lds, s)
-        : mode == kAdjPwl ? launch_one<float, kAdjPwl>(a, n_blocks, lds, s)
-                          : launch_one<float, kAdjAnalytic>(a, n_blocks, lds, s);
+    e = mode == kAdjNet           ? launch_one<float, kAdjNet>(a, n_blocks, lds, s)
+        : mode == kAdjNetSoftplus ? launch_one<float, kAdjNetSoftplus>(a, n_blocks, lds, s)
+        : mode == kAdjPwl         ? launch_one<float, kAdjPwl>(a, n_blocks, lds, s)
+                                  : launch_one<float, kAdjAnalytic>(a, n_blocks, lds, s);
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_adjoint_finalize, dim3(1), dim3(256), 0, s, a.partials, n_blocks,

@@ -1,7 +1,8 @@
 // Per-lane Seven-League kernels: one path per lane, one 64-path block per
 // workgroup.  Used for the FP64 mode (analytic map or network) and the FP32
-// analytic map.  The network path here is the plain double-precision
-// reference arithmetic on the GPU; the MFMA kernels carry the fast modes.
+// analytic map.  The network runs in double through net_lane.hpp
+// (activations in registers, weights in SGPRs); the MFMA kernels carry the
+// fast modes.
 //
 // Online stage of Algorithm I (steps 2-8): for each large step, collocation
 // points y_j from the analytic law or the network H (eq. 6.3/6.4), a fresh
@@ -10,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
+#include "net_lane.hpp"
 
 namespace sl7 {
 
@@ -17,40 +19,6 @@ template <typename T>
 __device__ __forceinline__ T act_fn(int act, T z) {
   if (act == SL7_RELU) return z > T(0) ? z : T(0);
   return z > T(0) ? z + log1p(exp(-z)) : log1p(exp(z));
-}
-
-// Network forward in double for one path per lane.  hA/hB: this lane's
-// columns of two LDS buffers [64 units][64 lanes].  First layer uses the
-// rank-one form z0 = wY * Y + c0 (dt and theta folded into c0 on the host).
-__device__ void net_lane_f64(const double* __restrict__ W, const double* __restrict__ c0,
-                             double Y, int m, int act, double* hA, double* hB,
-                             double y[kMaxM]) {
-  for (int o = 0; o < 64; ++o) hA[o * 64] = act_fn(act, fma(W[o], Y, c0[o]));
-  const double* Wl = W + 64;
-  double* hin = hA;
-  double* hout = hB;
-  for (int l = 0; l < 3; ++l) {
-    const double* bl = Wl + 64 * 64;
-    for (int o = 0; o < 64; ++o) {
-      double s = bl[o];
-      const double* row = Wl + o * 64;
-#pragma unroll 8
-      for (int k = 0; k < 64; ++k) s = fma(row[k], hin[k * 64], s);
-      hout[o * 64] = act_fn(act, s);
-    }
-    Wl += 64 * 64 + 64;
-    double* t = hin; hin = hout; hout = t;
-  }
-  const double* bh = Wl + 64 * m;
-#pragma unroll
-  for (int j = 0; j < kMaxM; ++j) {
-    if (j < m) {
-      double s = bh[j];
-      const double* row = Wl + j * 64;
-      for (int k = 0; k < 64; ++k) s = fma(row[k], hin[k * 64], s);
-      y[j] = s;
-    }
-  }
 }
 
 // Barycentric interpolation, second form, with the exact-node branch.
@@ -70,8 +38,16 @@ __device__ __forceinline__ T bary_lane(const T* xs, const T* ls, int m, const T 
   return hit ? yh : num / den;
 }
 
-template <typename T, bool NET>
-__global__ __launch_bounds__(64) void k_sim_lane(SimArgs a, int act) {
+// Waves per SIMD the register allocation aims at: the network keeps a
+// 64-entry FP64 activation vector per lane.
+template <bool NET>
+constexpr int lane_waves() { return NET ? 2 : 1; }
+
+// ACT: the network's hidden activation (SL7_RELU / SL7_SOFTPLUS; unused for
+// the analytic map).
+template <typename T, bool NET, int ACT>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, 64),
+                          amdgpu_waves_per_eu(lane_waves<NET>()))) void k_sim_lane(SimArgs a) {
   extern __shared__ double lds_h[];
   const InstDev& I = a.inst[0];
   const int lane = threadIdx.x;
@@ -102,8 +78,8 @@ __global__ __launch_bounds__(64) void k_sim_lane(SimArgs a, int act) {
         T y[kMaxM];
         if constexpr (NET) {
           if (Y < I.dom_lo || Y > I.dom_hi) ++ood;
-          net_lane_f64((const double*)a.wpack, I.c0d, (double)Y, m, act, lds_h + lane,
-                       lds_h + 64 * 64 + lane, (double*)y);
+          LaneMasks mk;
+          lane_net_fwd<T, kMaxM, ACT>(a.wpack, I.c0d, m, Y, y, mk, (T*)lds_h + lane);
         } else {
 #pragma unroll
           for (int j = 0; j < kMaxM; ++j) y[j] = A[j] * Y + B[j];
@@ -125,13 +101,16 @@ hipError_t launch_sim_lane(int prec, int use_net, int act, const SimArgs& a, int
   dim3 grid((unsigned)n_blocks), block(64);
   if (prec == SL7_F64) {
     if (use_net) {
-      const size_t lds = 2 * 64 * 64 * sizeof(double);
-      hipLaunchKernelGGL((k_sim_lane<double, true>), grid, block, lds, s, a, act);
+      const size_t lds = kLaneStageRows * 64 * sizeof(double);
+      if (act == SL7_RELU)
+        hipLaunchKernelGGL((k_sim_lane<double, true, SL7_RELU>), grid, block, lds, s, a);
+      else
+        hipLaunchKernelGGL((k_sim_lane<double, true, SL7_SOFTPLUS>), grid, block, lds, s, a);
     } else {
-      hipLaunchKernelGGL((k_sim_lane<double, false>), grid, block, 0, s, a, act);
+      hipLaunchKernelGGL((k_sim_lane<double, false, SL7_RELU>), grid, block, 0, s, a);
     }
   } else {
-    hipLaunchKernelGGL((k_sim_lane<float, false>), grid, block, 0, s, a, act);
+    hipLaunchKernelGGL((k_sim_lane<float, false, SL7_RELU>), grid, block, 0, s, a);
   }
   return hipGetLastError();
 }

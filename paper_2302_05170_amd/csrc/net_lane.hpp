@@ -1,5 +1,6 @@
-// One path per lane through a width-64 ReLU collocation network (eq. 6.3 /
-// 6.4), forward and reverse, with the lane's activation vector in registers.
+// One path per lane through a width-64 collocation network (eq. 6.3 / 6.4;
+// ReLU or Softplus hidden layers), forward and reverse, with the lane's
+// activation vector in registers.
 //
 // The weights are the same for every lane, so they are read through the
 // constant address space, which the compiler serves with scalar loads into
@@ -13,6 +14,8 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "../../include/sl7.h"
 
 namespace sl7 {
 
@@ -163,11 +166,132 @@ __device__ __forceinline__ void dense64(cptr<T> L, T (&v)[64], T* stage) {
   for (int o = 0; o < 32; ++o) v[o] = lo[o];
 }
 
-// Collocation points y[0..m) at Y; returns the ReLU masks.  c0 is the
-// instance's first-layer constant (bias plus the dt and theta inputs).
+// Softplus and its derivative (the logistic function), as the oracle
+// evaluates them: z + log1p(exp(-z)) for z > 0, log1p(exp(z)) otherwise,
+// written with one exp and one log1p (max(z, 0) adds an exact 0 below 0).
+template <typename T>
+__device__ __forceinline__ T softplus_lane(T z) {
+  return fmax(z, T(0)) + log1p(exp(-fabs(z)));
+}
+template <typename T>
+__device__ __forceinline__ T logistic_lane(T z) {
+  return T(1) / (T(1) + exp(-z));
+}
+
+// v[u] <- f(v[u]) for the 64 units with f's code instantiated for 8 units
+// only (a fully unrolled loop over 64 inlined transcendental functions is
+// too large for the compiler to unroll, and a rolled loop over a register
+// array would move the array to scratch memory): the units pass through the
+// lane's LDS column, 32 at a time, in a run-time loop over chunks of 8.
+template <typename T, typename F>
+__device__ __forceinline__ void map64(T (&v)[64], T* stage, F f) {
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i) stage[i * 64] = v[32 * half + i];
+#pragma unroll 1
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        T* p = stage + (8 * c + i) * 64;
+        *p = f(*p);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[32 * half + i] = stage[i * 64];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void softplus64(T (&v)[64], T* stage) {
+  map64<T>(v, stage, [](T z) { return softplus_lane(z); });
+}
+
+// First layer: v = wY * Y + c0 (rank one: dt and theta are folded into c0).
+template <typename T>
+__device__ __forceinline__ void first_layer(cptr<T> W, cptr<T> c0, T Y, T (&v)[64]) {
+#pragma unroll
+  for (int o = 0; o < 64; ++o) {
+    v[o] = fma(W[o], Y, c0[o]);
+    if ((o & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// y[j] = bh[j] + Wh[j] . h for j < m.
 template <typename T, int MAXM>
-__device__ __forceinline__ void lane_net_fwd(const void* net, const void* c0v, int m, T Y,
-                                             T (&y)[MAXM], LaneMasks& mk, T* stage) {
+__device__ __forceinline__ void head(cptr<T> W, int m, const T (&h)[64], T (&y)[MAXM]) {
+  cptr<T> Wh = W + kLaneHead;
+#pragma unroll
+  for (int j = 0; j < MAXM; ++j) {
+    T s = T(0);
+    if (j < m) {
+      s = Wh[8 * 64 + j];
+#pragma unroll
+      for (int k = 0; k < 64; ++k) {
+        s = fma(Wh[64 * j + k], h[k], s);
+        if ((k & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    y[j] = s;
+  }
+}
+
+// d = Wh^T ybar: the cotangent of the last hidden layer's output.
+template <typename T, int MAXM>
+__device__ __forceinline__ void head_vjp(cptr<T> W, int m, const T (&ybar)[MAXM], T (&d)[64]) {
+  cptr<T> Wh = W + kLaneHead;
+#pragma unroll
+  for (int k = 0; k < 64; ++k) d[k] = T(0);
+#pragma unroll
+  for (int j = 0; j < MAXM; ++j) {
+    if (j < m) {
+#pragma unroll
+      for (int k = 0; k < 64; ++k) {
+        d[k] = fma(Wh[64 * j + k], ybar[j], d[k]);
+        if ((k & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+}
+
+// Given d, the cotangent of the first layer's pre-activation: returns
+// d . dz/dY and adds d . dz/dtheta_k into thb[k] (FP64 weights, products and
+// sums).  wtheta holds the first-layer weights of the theta inputs times
+// their scales, [n_theta][64].
+template <typename T>
+__device__ __forceinline__ T first_layer_vjp(cptr<T> W, const void* wthv, int n_theta,
+                                             const T (&d)[64], double (&thb)[4]) {
+  T dY = T(0);
+#pragma unroll
+  for (int o = 0; o < 64; ++o) {
+    dY = fma(W[o], d[o], dY);
+    if ((o & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+  }
+  cptr<double> wt = as_cptr<double>(wthv);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (q < n_theta) {
+      double s = 0.0;
+#pragma unroll
+      for (int o = 0; o < 64; ++o) {
+        s = fma(wt[64 * q + o], (double)d[o], s);
+        if ((o & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+      }
+      thb[q] += s;
+    }
+  }
+  return dY;
+}
+
+// Collocation points y[0..m) at Y through a ReLU network; returns the
+// masks.  c0 is the instance's first-layer constant (bias plus the dt and
+// theta inputs).  The ReLU forward and reverse passes spell out the first
+// layer and the head instead of calling the helpers above: the FP64 sweep
+// runs at 256 VGPRs, and with the helpers the register allocator spilled
+// four times as much state inside the step loop (measured 5-30 % slower).
+template <typename T, int MAXM>
+__device__ __forceinline__ void lane_net_fwd_relu(const void* net, const void* c0v, int m, T Y,
+                                                  T (&y)[MAXM], LaneMasks& mk, T* stage) {
   cptr<T> W = as_cptr<T>(net);
   cptr<T> c0 = as_cptr<T>(c0v);
   T h[64];
@@ -258,6 +382,60 @@ __device__ __forceinline__ T lane_net_vjp(const void* net, const void* wthv, int
     }
   }
   return dY;
+}
+
+// Collocation points y[0..m) at Y.  c0 is the instance's first-layer
+// constant (bias plus the dt and theta inputs).  ACT is SL7_RELU (the masks
+// of the four hidden layers are returned in mk) or SL7_SOFTPLUS (mk unused).
+template <typename T, int MAXM, int ACT>
+__device__ __forceinline__ void lane_net_fwd(const void* net, const void* c0v, int m, T Y,
+                                             T (&y)[MAXM], LaneMasks& mk, T* stage) {
+  if constexpr (ACT == SL7_RELU) {
+    lane_net_fwd_relu<T, MAXM>(net, c0v, m, Y, y, mk, stage);
+  } else {
+    cptr<T> W = as_cptr<T>(net);
+    cptr<T> c0 = as_cptr<T>(c0v);
+    T h[64];
+    first_layer<T>(W, c0, Y, h);
+    softplus64<T>(h, stage);
+#pragma unroll 1
+    for (int l = 0; l < 3; ++l) {
+      dense64<T, false>(W + kLaneWy + l * kLaneLayer, h, stage);
+      softplus64<T>(h, stage);
+    }
+    head<T, MAXM>(W, m, h, y);
+  }
+}
+
+// The same through a Softplus network at Y.  Its derivatives are real
+// numbers, 256 per evaluation, too many to keep per lane; instead each
+// hidden layer's pre-activation is recomputed from Y when the reverse pass
+// reaches it (six 64x64 forward layers and three transposed ones per call).
+template <typename T, int MAXM>
+__device__ __forceinline__ T lane_net_vjp_softplus(const void* net, const void* c0v,
+                                                   const void* wthv, int m, int n_theta, T Y,
+                                                   const T (&ybar)[MAXM], double (&thb)[4],
+                                                   T* stage) {
+  cptr<T> W = as_cptr<T>(net);
+  cptr<T> c0 = as_cptr<T>(c0v);
+  T d[64];
+  head_vjp<T, MAXM>(W, m, ybar, d);
+#pragma unroll 1
+  for (int l = 3; l >= 0; --l) {
+    T z[64];
+    first_layer<T>(W, c0, Y, z);
+#pragma unroll 1
+    for (int q = 0; q < l; ++q) {
+      softplus64<T>(z, stage);
+      dense64<T, false>(W + kLaneWy + q * kLaneLayer, z, stage);
+    }
+    // z: pre-activation of hidden layer l; d: cotangent of its output
+    map64<T>(z, stage, [](T v) { return logistic_lane(v); });
+#pragma unroll
+    for (int u = 0; u < 64; ++u) d[u] *= z[u];
+    if (l > 0) dense64<T, true>(W + kLaneWy + (l - 1) * kLaneLayer, d, stage);
+  }
+  return first_layer_vjp<T>(W, wthv, n_theta, d, thb);
 }
 
 }  // namespace sl7

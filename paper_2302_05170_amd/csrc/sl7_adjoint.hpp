@@ -27,11 +27,12 @@ struct AdjArgs {
   double dA[4][kMaxM], dB[4][kMaxM];  // analytic map: d(A_j, B_j)/dtheta_k
 };
 
-// mode: 0 analytic map, 1 network (lane back-propagation), 2 piecewise-
-// linear form (a.net = table base).  prec F64 / PWL64 run in double.
+// mode: 0 analytic map, 1 ReLU network (lane back-propagation), 2 piecewise-
+// linear form (a.net = table base), 3 Softplus network.  prec F64 / PWL64
+// run in double.
 size_t adjoint_lds_bytes(int prec, int mode, int ckpt);
-// 32-bit words of evaluation state kept per path and step (8 network, 1
-// piecewise-linear, 0 analytic).
+// 32-bit words of evaluation state kept per path and step (8 ReLU network,
+// 1 piecewise-linear, 0 analytic and Softplus).
 int adjoint_state_words(int mode);
 hipError_t launch_adjoint(int prec, int mode, const AdjArgs& a, int64_t n_blocks, hipStream_t s);
 

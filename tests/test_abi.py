@@ -155,7 +155,7 @@ def test_plans_beyond_the_kernels_launch_bounds_are_rejected(L):
         assert rc == L.SL7_EINVAL, bad
 
 
-def test_narrow_softplus_network_accepted_by_forward_rejected_by_adjoint(L):
+def test_narrow_softplus_network_rejected_by_piecewise_linear_adjoint(L):
     import paper_2302_05170_amd as S
     p = W.glorot_params(5, 5, seed=2, width=W.OU_WIDTH)
     H = S.Mlp.create(5, 5, W.OU, p, [1.0] * 5, [0.0] * 5, W.OU_DOMAIN_LO, W.OU_DOMAIN_HI,
@@ -166,7 +166,7 @@ def test_narrow_softplus_network_accepted_by_forward_rejected_by_adjoint(L):
     pr = S.Problem(W.OU, (0.5, 0.3, 1.0), 0.2, 2.0, 8, 5, 100).c()
     g = L.Greeks()
     ws = ctypes.create_string_buffer(1 << 16)  # host memory; rejected before any use
-    rc = L.lib().sl7_adjoint(ctypes.byref(pr), H.handle, L.F64, 1, 1, 4, ctypes.byref(g), None,
+    rc = L.lib().sl7_adjoint(ctypes.byref(pr), H.handle, L.PWL64, 1, 1, 4, ctypes.byref(g), None,
                              ctypes.cast(ws, ctypes.c_void_p), len(ws), None)
     assert rc == L.SL7_EUNSUPPORTED and "ReLU" in L.lib().sl7_last_error().decode()
     # wider than the kernels' 64 units: a valid network, rejected by the simulator

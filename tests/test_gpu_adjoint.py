@@ -69,6 +69,55 @@ def test_per_path_sensitivities_match_oracle_tangents(S, H, Ho, case, payoff):
         assert abs(g["grad"][q] - df[:, q].mean()) <= 1e-11 * scale[q]
 
 
+OU_WEIGHTS = os.path.join(ROOT, "tests", "golden", "ou_mlp_5x50_softplus.sl7w")
+CIR_WEIGHTS = os.path.join(ROOT, "tests", "golden", "cir_mlp_5x64.sl7w")
+
+
+def check_pathwise(pp, f, df, g, tol=1e-10):
+    assert np.max(np.abs(pp[:, 0] - f)) <= 1e-12 * (1 + np.max(np.abs(f)))
+    scale = 1 + np.max(np.abs(df), axis=0)
+    err = np.max(np.abs(pp[:, 1:] - df), axis=0) / scale
+    assert np.all(err <= tol), err
+    for q in range(df.shape[1]):
+        assert abs(g["grad"][q] - df[:, q].mean()) <= 1e-11 * scale[q]
+    return err
+
+
+@pytest.mark.parametrize("payoff", [0, 1])
+def test_cir_network_adjoint_matches_oracle_tangents(S, payoff):
+    """CIR with its 5-input, 7-output ReLU network: three parameters, the
+    clamp at zero (a clamped step passes no gradient), FP64 per path."""
+    Hc, Hco = S.Mlp.load(CIR_WEIGHTS), oracle.load_mlp(CIR_WEIGHTS)
+    d = W.cir_instances(4)[2]
+    pr = S.Problem(d["model"], d["theta"], d["Y0"], d["T"], d["M"], d["m"], 3000,
+                   K=d["theta"][1])
+    g, pp = S.adjoint(pr, Hc, prec="f64", seed=9, payoff=payoff, ckpt_every=3, per_path=True)
+    f, df = oracle_pathwise(pr, Hco, 9, payoff, pr.N)
+    err = check_pathwise(pp.cpu().numpy(), f, df, g)
+    print("cir network", payoff, "max pathwise gradient error", err)
+
+
+@pytest.mark.parametrize("payoff", [0, 1])
+def test_softplus_network_adjoint_matches_oracle_tangents(S, payoff):
+    """The paper's network (4 x 50 Softplus, padded to 64) on the OU model:
+    the reverse pass recomputes each layer's pre-activation for the logistic
+    derivative; FP64 per path against the oracle's dual-number pass, with
+    ragged N and a checkpoint interval that does not divide M."""
+    Ho_, Hoo = S.Mlp.load(OU_WEIGHTS), oracle.load_mlp(OU_WEIGHTS)
+    P = W.OU_PAPER
+    pr = S.Problem(P["model"], P["theta"], P["Y0"], P["T"], P["M"], P["m"], 1000, K=P["K"])
+    g, pp = S.adjoint(pr, Ho_, prec="f64", seed=P["seed"], payoff=payoff, ckpt_every=3,
+                      per_path=True)
+    f, df = oracle_pathwise(pr, Hoo, P["seed"], payoff, pr.N)
+    err = check_pathwise(pp.cpu().numpy(), f, df, g)
+    print("ou softplus", payoff, "max pathwise gradient error", err)
+    g32 = S.adjoint(pr, Ho_, prec="f32", seed=P["seed"], payoff=payoff, ckpt_every=3)
+    for a, b, se in zip(g32["grad"], g["grad"], g["grad_se"]):
+        assert abs(a - b) <= 1e-4 * abs(b) + 1e-3 * se, (a, b)
+    for k in (1, 8):
+        assert S.adjoint(pr, Ho_, prec="f64", seed=P["seed"], payoff=payoff, ckpt_every=k) == g
+
+
 def test_checkpoint_interval_does_not_change_results(S, H):
     pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 16, 5, 3000, K=1.0)
     ref = S.adjoint(pr, H, prec="f64", seed=3, payoff=1, ckpt_every=1)
