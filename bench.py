@@ -131,7 +131,8 @@ def main():
     ap.add_argument("--cpu-paths", type=int, default=2 ** 21)
     ap.add_argument("--profile-run", default=None,
                     help="only run the default workload in this precision (plus a 256 MiB "
-                         "calibration copy) for rocprofv3; prints no JSON")
+                         "calibration copy) for rocprofv3; prints no JSON.  adjoint_f64 / "
+                         "adjoint_f32: the adjoint workload's sweep instead")
     ap.add_argument("--grab", type=int, default=None,
                     help="with --profile-run: 64-path blocks per work-queue grab (default plan "
                          "otherwise)")
@@ -161,6 +162,16 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log(f"calibration copy: {src.numel() * 4} bytes read and written")
+        if args.profile_run.startswith("adjoint_"):
+            ga = W.CONFIGS["gbm_adjoint_2p22x16"]
+            pra = S.Problem(ga["model"], ga["theta"], ga["Y0"], ga["T"], ga["M"], ga["m"], ga["N"],
+                            K=ga["K"])
+            prec = args.profile_run[len("adjoint_"):]
+            for _ in range(args.steps):
+                S.adjoint(pra, H, prec=prec, seed=ga["seed"], payoff=1, ckpt_every=ga["ckpt"])
+            torch.cuda.synchronize()
+            log(f"profile run: {args.steps} adjoint sweeps in {prec}, N={ga['N']}, M={ga['M']}")
+            return
         plan = None
         if args.grab is not None:
             plan = dict(waves_per_block=4, blocks_per_cu=2 if args.profile_run != "f32" else 1,
@@ -258,6 +269,20 @@ def main():
                     "mean_YT": st_o["mean"][0], "paper_mx150_s": PAPER_T61_PARALLEL_S[n]}
             log(f"OU 4x50 softplus {prec}: " + ", ".join(
                 f"N={k} {v['ms_per_run']:.3f} ms" for k, v in ou[prec].items()))
+        # pathwise Greeks of E[max(Y_T - K, 0)] w.r.t. (Y0, ybar, sigma, lambda) through
+        # the Softplus network, at the largest path count
+        n = max(P["path_counts"])
+        pro = S.Problem(P["model"], P["theta"], P["Y0"], P["T"], P["M"], P["m"], n, K=P["K"])
+        for prec in ("f64", "f32"):
+            S.adjoint(pro, Hou, prec=prec, seed=P["seed"], payoff=1, ckpt_every=4)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g = S.adjoint(pro, Hou, prec=prec, seed=P["seed"], payoff=1, ckpt_every=4)
+            dt = time.perf_counter() - t0
+            ou.setdefault("adjoint", {})[prec] = {
+                "paths": n, "seconds": dt, "s_per_greek": dt / len(g["grad"]),
+                "greeks": g["grad"], "greeks_se": g["grad_se"]}
+            log(f"OU softplus adjoint {prec}: {dt * 1e3:.1f} ms for {len(g['grad'])} Greeks")
 
     # trainer: one epoch over 2^16 labels, batch 1024
     feats = torch.tensor(W.gbm_features(W.N_LABELS), dtype=torch.float32, device="cuda")
