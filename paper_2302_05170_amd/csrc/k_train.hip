@@ -32,7 +32,13 @@ __device__ __forceinline__ void drift_diffusion(int model, const double* th, dou
   }
 }
 
-__global__ __launch_bounds__(256) void k_em_labels(LabelArgs a) {
+// One label per workgroup at a time: 1024 threads (four waves per SIMD: the
+// endpoints' LDS array, up to 128 KB, allows one workgroup per CU, and the
+// FP64 Box-Muller and Euler steps need several waves per SIMD to hide their
+// latencies).
+constexpr int kLabelThreads = 1024;
+
+__global__ __launch_bounds__(kLabelThreads) void k_em_labels(LabelArgs a) {
   extern __shared__ double ends[];
   const int tid = threadIdx.x;
   for (int64_t L = blockIdx.x; L < a.n_labels; L += gridDim.x) {
@@ -100,7 +106,7 @@ hipError_t launch_em_labels(const LabelArgs& a, hipStream_t s) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = (int)std::min<int64_t>(a.n_labels, 65535);
-  hipLaunchKernelGGL(k_em_labels, dim3(grid), dim3(256), lds, s, a);
+  hipLaunchKernelGGL(k_em_labels, dim3(grid), dim3(kLabelThreads), lds, s, a);
   return hipGetLastError();
 }
 
