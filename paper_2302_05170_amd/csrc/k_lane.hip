@@ -72,9 +72,14 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, 64),
     const u32x4 r = philox_step_quad(a.seed, (uint32_t)(i0 >> 2), gp, tag);
     T xq[4];
     if constexpr (F64) normals4_f64(r, xq); else normals4_f32(r, xq);
-#pragma unroll
+    // unrolled for the analytic map; with the network the body is too large
+    // to unroll, so the step's normal is chosen by selects (an indexed read
+    // of xq would place it in scratch memory)
+    constexpr int kUnroll = NET ? 1 : 4;
+#pragma unroll kUnroll
     for (int u = 0; u < 4; ++u) {
       if (i0 + u < M) {
+        const T X = u == 0 ? xq[0] : (u == 1 ? xq[1] : (u == 2 ? xq[2] : xq[3]));
         T y[kMaxM];
         if constexpr (NET) {
           if (Y < I.dom_lo || Y > I.dom_hi) ++ood;
@@ -84,7 +89,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, 64),
 #pragma unroll
           for (int j = 0; j < kMaxM; ++j) y[j] = A[j] * Y + B[j];
         }
-        Y = bary_lane<T>(xs, ls, m, y, xq[u]);
+        Y = bary_lane<T>(xs, ls, m, y, X);
         if (I.clamp_zero && Y < T(0)) { Y = T(0); ++clamped; }
       }
     }
