@@ -577,7 +577,9 @@ int default_plan(int prec, sl7_plan* p) {
   // register-limited occupancy of the MFMA kernels; the lane kernels of the
   // piecewise-linear form hide their table loads with more waves
   p->blocks_per_cu = is_pwl(prec) ? 8 : is_half(prec) ? 2 : 1;
-  p->grab = 1;
+  // the piecewise-linear kernel's blocks are short: four per work-queue
+  // atomic (measured 5 % faster than one)
+  p->grab = is_pwl(prec) ? 4 : 1;
   p->reserved = 0;
   return SL7_OK;
 }
