@@ -25,6 +25,7 @@ using cptr = const __attribute__((address_space(4))) T*;
 // The pointer passes through an empty asm statement, so that the compiler
 // cannot hoist the weight loads of one network evaluation out of the loop
 // over steps: hundreds of loop-invariant weights would not fit in SGPRs.
+// p must be the same in every lane of the wave (it is held in SGPRs).
 template <typename T>
 __device__ __forceinline__ cptr<T> as_cptr(const void* p) {
   uint64_t v = (uint64_t)(uintptr_t)p;
