@@ -118,6 +118,28 @@ def test_softplus_network_adjoint_matches_oracle_tangents(S, payoff):
         assert S.adjoint(pr, Ho_, prec="f64", seed=P["seed"], payoff=payoff, ckpt_every=k) == g
 
 
+def test_adjoint_full_size_sampled_paths(S, H, Ho):
+    """The adjoint workload at full size (N = 2^22, M = 16, checkpoint every
+    4, the launch bench.py times): per-path df/d(Y0, sigma, mu) in FP64 on
+    2048 sampled paths (first, last and strided) against the oracle's
+    dual-number pass on the same global path indices."""
+    c = W.CONFIGS["gbm_adjoint_2p22x16"]
+    pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
+    g, pp = S.adjoint(pr, H, prec="f64", seed=c["seed"], payoff=1, ckpt_every=c["ckpt"],
+                      per_path=True)
+    idx = np.unique(np.concatenate([np.arange(512), np.arange(pr.N - 512, pr.N),
+                                    np.linspace(0, pr.N - 1, 1024).astype(np.int64)]))
+    pp = pp[torch.from_numpy(idx).cuda()].cpu().numpy()
+    opr = oracle.Problem(pr.model, pr.theta, pr.Y0, pr.T, pr.M, pr.m, pr.instance)
+    YT, dY = oracle.simulate_tangent(opr, Ho, c["seed"], idx)
+    ind = (YT > pr.K).astype(float)
+    f, df = np.maximum(YT - pr.K, 0.0), dY * ind[:, None]
+    assert np.max(np.abs(pp[:, 0] - f)) <= 1e-12 * (1 + np.max(np.abs(f)))
+    err = np.max(np.abs(pp[:, 1:] - df), axis=0) / (1 + np.max(np.abs(df), axis=0))
+    print("full-size sampled pathwise gradient error", err)
+    assert np.all(err <= 1e-10)
+
+
 def test_checkpoint_interval_does_not_change_results(S, H):
     pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 16, 5, 3000, K=1.0)
     ref = S.adjoint(pr, H, prec="f64", seed=3, payoff=1, ckpt_every=1)
