@@ -219,13 +219,14 @@ def main():
                      K=d["theta"][1], instance=d["instance"]) for d in W.cir_instances(256)]
     ps4 = sum(p.N * p.M for p in prs)
     batched = {}
-    # the tuner times candidate plans on one instance of the largest N (all
-    # instances share d_in and m, the tuner's cache key)
-    big = max(prs, key=lambda p: p.N * p.M)
+    # the batch tuner times every candidate plan on the 256 instances themselves
+    # (not run for the FP32 comparator: 55 candidates of 60 ms launches)
     for prec in ("bf16x3", "bf16", "f32", "pwl32"):
-        tuned = S.autotune(big, Hc, prec=prec)
+        tuned = S.autotune_batched(prs, Hc, prec=prec) if prec != "f32" else None
         row = {"tuned_plan": tuned}
         for name, plan in (("default", None), ("tuned", tuned)):
+            if name == "tuned" and tuned is None:
+                continue
             S.simulate_batched(prs, Hc, prec=prec, seed=11, plan=plan, use_graph=True)
             reps = 5 if prec != "f32" else 2
             t0 = time.perf_counter()

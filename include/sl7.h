@@ -294,6 +294,14 @@ int sl7_train_grad(const sl7_mlp* H, const float* X_dev, const float* Y_dev, int
 int sl7_autotune(const sl7_problem* shape, const sl7_mlp* H, int prec,
                  const char* cache_path, sl7_plan* out, void* stream);
 
+/* The same for a batch: times each candidate plan on the n instances of
+ * prs[] themselves, one persistent launch as sl7_simulate_batched makes it
+ * (arguments checked as there), and returns the fastest in *out.  The cache
+ * key adds a hash of the instances' shapes (model, m, M, N of each, in
+ * order).  Synchronises `stream`. */
+int sl7_autotune_batched(const sl7_problem* prs, int n, const sl7_mlp* H, int prec,
+                         const char* cache_path, sl7_plan* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -194,6 +194,18 @@ def autotune(shape: Problem, H: Mlp, prec="bf16x3", cache_path: str | None = Non
             "grab": plan.grab}
 
 
+def autotune_batched(prs: list, H: Mlp, prec="bf16x3", cache_path: str | None = None,
+                     stream=None) -> dict:
+    """Fastest launch plan for the batch prs itself (sl7_autotune_batched)."""
+    arr = (L.Problem * len(prs))(*[p.c() for p in prs])
+    plan = L.Plan()
+    L.check(L.lib().sl7_autotune_batched(arr, len(prs), H.handle, _prec(prec),
+                                         cache_path.encode() if cache_path else None,
+                                         ctypes.byref(plan), _stream(stream)))
+    return {"waves_per_block": plan.waves_per_block, "blocks_per_cu": plan.blocks_per_cu,
+            "grab": plan.grab}
+
+
 def simulate_batched(prs: list, H: Mlp, prec="bf16", seed: int = 11, plan: dict | None = None,
                      use_graph: bool = True, stream=None) -> list:
     """Runs sl7_simulate_batched; returns one stats dict per instance."""

@@ -214,6 +214,71 @@ bool cache_lookup(const char* path, const std::string& key, sl7_plan* out) {
 
 }  // namespace
 
+namespace {
+
+// Times every candidate plan on the n prepared instances and returns the
+// fastest.  The default plan comes first and a candidate must beat the best
+// so far by 2 % to replace it, so timing noise does not pick a plan.
+int time_candidates(const sl7_problem* prs, int n, Mlp* H, int prec, hipStream_t s, Workspace& ws,
+                    sl7_plan* bestp_out, float* best_out) {
+  std::vector<sl7_plan> cands(1);
+  default_plan(prec, &cands[0]);
+  const int wpb[] = {1, 2, 4};
+  const int bpc[] = {1, 2, 3, 4, 8, 16};
+  const int grabs[] = {1, 4};
+  for (int w : wpb)
+    for (int b : bpc)
+      for (int g : grabs) {
+        if (w * b > 32) continue;
+        sl7_plan p = {w, b, g, 0};
+        if (p.waves_per_block == cands[0].waves_per_block && p.blocks_per_cu == cands[0].blocks_per_cu &&
+            p.grab == cands[0].grab)
+          continue;
+        cands.push_back(p);
+      }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(SL7_EHIP, "hipEventCreate");
+  SimArgs a;
+  int rc = prepare_instances(prs, n, H, prec, 1, nullptr, s, ws, a);
+  float best = INFINITY;
+  sl7_plan bestp = cands[0];
+  for (size_t c = 0; c < cands.size() && !rc; ++c) {
+    rc = launch_instances(a, n, prs[0].N, H, prec, cands[c], s, ws);  // warm-up
+    float ms = INFINITY;
+    for (int t = 0; t < 2 && !rc; ++t) {  // best of two timings of three launches
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && !rc; ++r) rc = launch_instances(a, n, prs[0].N, H, prec, cands[c], s, ws);
+      (void)hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SL7_EHIP, "hipEventSynchronize"); break; }
+      float t_ms = 0.f;
+      (void)hipEventElapsedTime(&t_ms, e0, e1);
+      ms = std::min(ms, t_ms);
+    }
+    if (rc) break;
+    if (c == 0 || ms < 0.98f * best) { best = ms; bestp = cands[c]; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  *bestp_out = bestp;
+  *best_out = best / 3.f;
+  return SL7_OK;
+}
+
+int cache_store(const char* cache_path, const std::string& key, const sl7_plan& p, float ms,
+                int64_t path_steps) {
+  FILE* f = fopen(cache_path, "a");
+  if (!f) return fail(SL7_EIO, "cannot append to %s", cache_path);
+  fprintf(f, "{\"key\": \"%s\", \"waves_per_block\": %d, \"blocks_per_cu\": %d, \"grab\": %d, "
+             "\"ms_per_launch\": %.5f, \"path_steps\": %lld}\n",
+          key.c_str(), p.waves_per_block, p.blocks_per_cu, p.grab, ms, (long long)path_steps);
+  fclose(f);
+  return SL7_OK;
+}
+
+}  // namespace
+
 extern "C" int sl7_autotune(const sl7_problem* shape, const sl7_mlp* Hc, int prec,
                             const char* cache_path, sl7_plan* out, void* stream) {
   Mlp* H = const_cast<Mlp*>(reinterpret_cast<const Mlp*>(Hc));
@@ -231,62 +296,49 @@ extern "C" int sl7_autotune(const sl7_problem* shape, const sl7_mlp* Hc, int pre
   if (rc) return rc;
   Workspace& ws = workspace(dev);
   std::lock_guard<std::mutex> lk(ws.mu);
-  hipStream_t s = (hipStream_t)stream;
-  // the default plan first: a candidate must beat it by 2 % to replace it,
-  // so timing noise does not pick a plan
-  std::vector<sl7_plan> cands(1);
-  default_plan(prec, &cands[0]);
-  const int wpb[] = {1, 2, 4};
-  const int bpc[] = {1, 2, 3, 4, 8, 16};
-  const int grabs[] = {1, 4};
-  for (int w : wpb)
-    for (int b : bpc)
-      for (int g : grabs) {
-        if (w * b > 32) continue;
-        sl7_plan p = {w, b, g, 0};
-        if (p.waves_per_block == cands[0].waves_per_block && p.blocks_per_cu == cands[0].blocks_per_cu &&
-            p.grab == cands[0].grab)
-          continue;
-        cands.push_back(p);
-      }
   // time on at least 2^20 paths so that each launch fills the chip for
   // several milliseconds
   sl7_problem sh = *shape;
   sh.N = std::max<int64_t>(shape->N, int64_t(1) << 20);
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-    return fail(SL7_EHIP, "hipEventCreate");
-  SimArgs a;
-  rc = prepare_instances(&sh, 1, H, prec, 1, nullptr, s, ws, a);
-  float best = INFINITY;
-  sl7_plan bestp = cands[0];
-  for (size_t c = 0; c < cands.size() && !rc; ++c) {
-    rc = launch_instances(a, 1, sh.N, H, prec, cands[c], s, ws);  // warm-up
-    float ms = INFINITY;
-    for (int t = 0; t < 2 && !rc; ++t) {  // best of two timings of three launches
-      (void)hipEventRecord(e0, s);
-      for (int r = 0; r < 3 && !rc; ++r) rc = launch_instances(a, 1, sh.N, H, prec, cands[c], s, ws);
-      (void)hipEventRecord(e1, s);
-      if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(SL7_EHIP, "hipEventSynchronize"); break; }
-      float t_ms = 0.f;
-      (void)hipEventElapsedTime(&t_ms, e0, e1);
-      ms = std::min(ms, t_ms);
-    }
-    if (rc) break;
-    if (c == 0 || ms < 0.98f * best) { best = ms; bestp = cands[c]; }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  sl7_plan best;
+  float ms = 0.f;
+  rc = time_candidates(&sh, 1, H, prec, (hipStream_t)stream, ws, &best, &ms);
   if (rc) return rc;
-  *out = bestp;
-  if (cache_path) {
-    FILE* f = fopen(cache_path, "a");
-    if (!f) return fail(SL7_EIO, "cannot append to %s", cache_path);
-    fprintf(f, "{\"key\": \"%s\", \"waves_per_block\": %d, \"blocks_per_cu\": %d, \"grab\": %d, "
-               "\"ms_per_launch\": %.5f, \"N\": %lld, \"M\": %d}\n",
-            key.c_str(), bestp.waves_per_block, bestp.blocks_per_cu, bestp.grab, best / 3.0,
-            (long long)sh.N, sh.M);
-    fclose(f);
+  *out = best;
+  return cache_path ? cache_store(cache_path, key, best, ms, sh.N * sh.M) : SL7_OK;
+}
+
+extern "C" int sl7_autotune_batched(const sl7_problem* prs, int n, const sl7_mlp* Hc, int prec,
+                                    const char* cache_path, sl7_plan* out, void* stream) {
+  Mlp* H = const_cast<Mlp*>(reinterpret_cast<const Mlp*>(Hc));
+  if (!out) return fail(SL7_EINVAL, "out is NULL");
+  int rc = check_batch(prs, n, H, prec);
+  if (rc) return rc;
+  // the key names the batch by its shapes: model, m, M and N of every instance
+  uint64_t h = fnv1a(&n, sizeof(n));
+  for (int k = 0; k < n; ++k) {
+    const int32_t v[3] = {prs[k].model, prs[k].m, prs[k].M};
+    h = fnv1a(v, sizeof(v), h);
+    h = fnv1a(&prs[k].N, sizeof(prs[k].N), h);
   }
-  return SL7_OK;
+  char hb[40];
+  snprintf(hb, sizeof(hb), "/batch%016llx", (unsigned long long)h);
+  const std::string key = plan_key(prec, H) + hb;
+  if (cache_path && cache_lookup(cache_path, key, out)) return SL7_OK;
+  rc = H->ensure_device(prec);
+  if (rc) return rc;
+  int dev;
+  rc = current_device(&dev);
+  if (rc) return rc;
+  Workspace& ws = workspace(dev);
+  std::lock_guard<std::mutex> lk(ws.mu);
+  std::vector<sl7_problem> p(prs, prs + n);
+  sl7_plan best;
+  float ms = 0.f;
+  rc = time_candidates(p.data(), n, H, prec, (hipStream_t)stream, ws, &best, &ms);
+  if (rc) return rc;
+  *out = best;
+  int64_t ps = 0;
+  for (int k = 0; k < n; ++k) ps += prs[k].N * prs[k].M;
+  return cache_path ? cache_store(cache_path, key, best, ms, ps) : SL7_OK;
 }

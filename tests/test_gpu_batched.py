@@ -115,3 +115,23 @@ def test_autotune_returns_valid_plan_and_caches(S, H):
         assert (plan2.waves_per_block, plan2.blocks_per_cu, plan2.grab) == \
             (plan.waves_per_block, plan.blocks_per_cu, plan.grab)
         assert open(path).read() == text  # second call read the cache
+
+
+def test_autotune_batched_times_the_batch_and_caches(S, H):
+    """The batch tuner returns a valid plan under a key naming the batch's
+    shapes, reads it back, and the plan's results equal the default plan's."""
+    prs = problems(S, 24)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "plans.jsonl")
+        plan = S.autotune_batched(prs, H, prec="bf16x3", cache_path=path)
+        assert plan["waves_per_block"] in (1, 2, 4) and 1 <= plan["blocks_per_cu"] <= 16
+        text = open(path).read()
+        assert '"key": "gfx950/prec4/din5/m7/batch' in text
+        assert S.autotune_batched(prs, H, prec="bf16x3", cache_path=path) == plan
+        assert open(path).read() == text  # second call read the cache
+        # another batch gets its own key
+        S.autotune_batched(prs[:5], H, prec="bf16x3", cache_path=path)
+        assert len(open(path).read().splitlines()) == 2
+    tuned = S.simulate_batched(prs, H, prec="bf16x3", seed=11, plan=plan, use_graph=False)
+    ref = S.simulate_batched(prs, H, prec="bf16x3", seed=11, use_graph=False)
+    assert tuned == ref
