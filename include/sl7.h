@@ -203,8 +203,8 @@ int sl7_pwl_compile(const sl7_mlp* H, const sl7_problem* pr, int max_pieces, int
                     double* brk, double* anchor, double* slope, double* value);
 
 /* Many instances of uneven size in one persistent launch (network map,
- * prec F32/BF16/F16/BF16X3/F16X3/PWL32).  Work is 64-path blocks ordered longest-M first and
- * handed out by an atomic work counter; per-instance statistics go to
+ * every prec but F64; all instances share m).  Work is 64-path blocks
+ * ordered longest-M first and handed out by an atomic work counter; per-instance statistics go to
  * stats_host[n] (synchronises the stream).  The launch sequence is captured
  * once into a hipGraph per distinct (prec, instance table) signature and
  * replayed when use_graph != 0. */
