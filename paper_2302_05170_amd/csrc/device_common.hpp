@@ -44,13 +44,16 @@ __device__ __forceinline__ u32x4 philox_step_quad(uint64_t seed, uint32_t q, int
 }
 
 // Box-Muller in double: u = (r + 1/2) 2^-32, X = sqrt(-2 ln u_a) (cos, sin)(2 pi u_b).
+// The angle goes to sincospi as 2 u_b, which is exact: one shared, exact
+// range reduction instead of two reductions of the rounded product 2 pi u_b.
 __device__ __forceinline__ void box_muller_f64(uint32_t ra, uint32_t rb, double& x0, double& x1) {
   const double ua = ((double)ra + 0.5) * 0x1p-32;
   const double ub = ((double)rb + 0.5) * 0x1p-32;
   const double rad = sqrt(-2.0 * log(ua));
-  const double ang = (2.0 * 3.14159265358979323846) * ub;
-  x0 = rad * cos(ang);
-  x1 = rad * sin(ang);
+  double sn, cs;
+  sincospi(2.0 * ub, &sn, &cs);
+  x0 = rad * cs;
+  x1 = rad * sn;
 }
 
 // Box-Muller in float, accurate over the whole range: the logarithm uses
