@@ -304,8 +304,11 @@ def main():
     achieved = FLOPS_PER_PATH_STEP * ps / t_kernel
     se_pair = math.hypot(b["st"]["se"][0], res["f32"]["st"]["se"][0])
     out = {
-        "metric": "7L path-steps/s (BF16 MFMA network GEMMs, three-pass split, FP32 interpolation, "
-                  "FP64 mean)",
+        "metric": "7L path-steps/s (bf16 MFMA vs fp32) at fixed error; MFMA util; adjoint s/Greek",
+        "metric_detail": "value: path-steps/s of the BF16 MFMA network GEMMs (three-pass split, FP32 "
+                         "interpolation, FP64 mean) at the per-path error bound 2e-3; FP32 MFMA "
+                         "beside it in speedup_vs_f32_mfma; MFMA util in mfma_busy_rocprof; "
+                         "adjoint s/Greek in adjoint_gbm_2p22x16",
         "value": ps / b["wall"],
         "unit": "path-steps/s",
         "n_gpus": 1,
