@@ -270,7 +270,9 @@ typedef struct {
 } sl7_train_spec;
 
 /* Trains H in place (FP32 forward/backward kernels, deterministic gradient
- * sums).  X_dev [n x d_in] raw inputs, Y_dev [n x m] labels (device, FP32).
+ * sums).  H: 4 hidden layers of at most 64 units, ReLU or Softplus
+ * (EUNSUPPORTED otherwise).  X_dev [n x d_in] raw inputs, Y_dev [n x m]
+ * labels (device, FP32).
  * order_dev: NULL (rows in order every epoch) or epochs x n int32 row
  * indices (device); each epoch takes n / batch minibatches of consecutive
  * entries.  loss_hist_host: NULL or room for epochs * (n / batch) doubles

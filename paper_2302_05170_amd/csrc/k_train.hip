@@ -114,11 +114,15 @@ hipError_t launch_em_labels(const LabelArgs& a, hipStream_t s) {
 // Training: forward + backward of 64 samples per workgroup on FP32 MFMA
 // (v_mfma_f32_16x16x4_f32).  Four waves; in every product the 64 samples
 // are four 16-column tiles.  Parameter layout: per layer W (out x in,
-// row-major) then b; hidden layers l = 0..3 give H_{l+1} = ReLU(W_l H_l +
-// b_l), the head y = W_4 H_4 + b_4.
+// row-major) then b; hidden layers l = 0..3 give H_{l+1} = act(W_l H_l +
+// b_l), the head y = W_4 H_4 + b_4.  Hidden layers of width < 64 run padded
+// to 64 units whose activations are held at 0 (so they feed nothing and
+// receive no gradient).
 //   forward   wave w: units 16w..16w+15 of each hidden layer, all samples;
 //             the head (m <= 8 rows, padded to 16) one sample tile per wave
-//   backward  dZ_l = (W_{l+1}^T dZ_{l+1}) * [H_{l+1} > 0], same split
+//   backward  dZ_l = (W_{l+1}^T dZ_{l+1}) * act'(Z_{l+1}), same split;
+//             act' from the stored activation: [H > 0] for ReLU, and for
+//             Softplus the logistic function 1 - exp(-H)
 //   gradient  dW_l = dZ_l H_l^T over the 64 samples (K = samples), tiles
 //             spread over the waves; bias sums in a fixed order
 // MFMA operand layout (16x16x4): lane (g = l/16, r = l%16) gives A[r][g]
@@ -128,6 +132,15 @@ constexpr int kTS = 65;  // LDS row stride of the [unit][sample] buffers (bank s
 
 __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float train_act(int act, float z) {
+  return act == SL7_RELU ? fmaxf(z, 0.f) : fmaxf(z, 0.f) + log1pf(expf(-fabsf(z)));
+}
+
+// act'(z) from h = act(z): ReLU [h > 0]; Softplus 1 / (1 + e^-z) = 1 - e^-h.
+__device__ __forceinline__ float train_act_deriv(int act, float h) {
+  return act == SL7_RELU ? (h > 0.f ? 1.f : 0.f) : -expm1f(-h);
 }
 
 __global__ __launch_bounds__(256) void k_fwd_bwd(TrainArgs a, int64_t base) {
@@ -142,12 +155,12 @@ __global__ __launch_bounds__(256) void k_fwd_bwd(TrainArgs a, int64_t base) {
   float* dY = sh + 8 * kTS + 8 * 64 * kTS;
   __shared__ float red[4];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63, g = lane >> 4, r = lane & 15;
-  const int din = a.d_in, m = a.m;
+  const int din = a.d_in, m = a.m, Wd = a.width, act = a.act;
   const float* P = a.params;
   int64_t off[5];
   off[0] = 0;
-  off[1] = 64 * din + 64;
-  for (int l = 2; l <= 4; ++l) off[l] = off[l - 1] + 64 * 64 + 64;
+  off[1] = (int64_t)Wd * din + Wd;
+  for (int l = 2; l <= 4; ++l) off[l] = off[l - 1] + (int64_t)Wd * Wd + Wd;
   // inputs (rows >= d_in zero)
   for (int i = t; i < 8 * 64; i += 256) {
     const int k = i >> 6, sidx = i & 63;
@@ -159,33 +172,39 @@ __global__ __launch_bounds__(256) void k_fwd_bwd(TrainArgs a, int64_t base) {
   __syncthreads();
   // forward through the hidden layers
   for (int l = 0; l < 4; ++l) {
-    const int nin = l == 0 ? din : 64;
+    const int nin = l == 0 ? din : Wd;
     const int kpad = l == 0 ? 8 : 64;
     const float* W = P + off[l];
-    const float* b = W + 64 * nin;
+    const float* b = W + (int64_t)Wd * nin;
     const int u = 16 * w + r;  // this lane's A row (unit)
     f32x4 acc[4];
     for (int st = 0; st < 4; ++st)
-      for (int i = 0; i < 4; ++i) acc[st][i] = b[16 * w + 4 * g + i];
+      for (int i = 0; i < 4; ++i) {
+        const int unit = 16 * w + 4 * g + i;
+        acc[st][i] = unit < Wd ? b[unit] : 0.f;
+      }
     for (int kb = 0; kb < kpad / 4; ++kb) {
       const int k = 4 * kb + g;
-      const float av = k < nin ? W[u * nin + k] : 0.f;
+      const float av = (k < nin && u < Wd) ? W[u * nin + k] : 0.f;
       for (int st = 0; st < 4; ++st) acc[st] = mfma4(av, H[l][k * kTS + 16 * st + r], acc[st]);
     }
     for (int st = 0; st < 4; ++st)
-      for (int i = 0; i < 4; ++i) H[l + 1][(16 * w + 4 * g + i) * kTS + 16 * st + r] = fmaxf(acc[st][i], 0.f);
+      for (int i = 0; i < 4; ++i) {
+        const int unit = 16 * w + 4 * g + i;
+        H[l + 1][unit * kTS + 16 * st + r] = unit < Wd ? train_act(act, acc[st][i]) : 0.f;
+      }
     __syncthreads();
   }
   // head and residuals: wave w takes samples 16w..16w+15
   float sq = 0.f;
   {
     const float* Wh = P + off[4];
-    const float* bh = Wh + 64 * m;
+    const float* bh = Wh + (int64_t)Wd * m;
     f32x4 acc;
     for (int i = 0; i < 4; ++i) acc[i] = (4 * g + i) < m ? bh[4 * g + i] : 0.f;
     for (int kb = 0; kb < 16; ++kb) {
       const int k = 4 * kb + g;
-      const float av = r < m ? Wh[r * 64 + k] : 0.f;
+      const float av = (r < m && k < Wd) ? Wh[r * Wd + k] : 0.f;
       acc = mfma4(av, H[4][k * kTS + 16 * w + r], acc);
     }
     const int sidx = 16 * w + r;
@@ -212,29 +231,30 @@ __global__ __launch_bounds__(256) void k_fwd_bwd(TrainArgs a, int64_t base) {
       const float* Wh = P + off[4];
       for (int kb = 0; kb < 2; ++kb) {
         const int j = 4 * kb + g;
-        const float av = j < m ? Wh[j * 64 + u] : 0.f;
+        const float av = (j < m && u < Wd) ? Wh[j * Wd + u] : 0.f;
         for (int st = 0; st < 4; ++st) acc[st] = mfma4(av, dY[j * kTS + 16 * st + r], acc[st]);
       }
     } else {
       const float* Wn = P + off[l + 1];
       for (int kb = 0; kb < 16; ++kb) {
         const int o = 4 * kb + g;
-        const float av = Wn[o * 64 + u];
+        const float av = (o < Wd && u < Wd) ? Wn[o * Wd + u] : 0.f;
         for (int st = 0; st < 4; ++st) acc[st] = mfma4(av, D[l + 1][o * kTS + 16 * st + r], acc[st]);
       }
     }
     for (int st = 0; st < 4; ++st)
       for (int i = 0; i < 4; ++i) {
         const int unit = 16 * w + 4 * g + i, sidx = 16 * st + r;
-        D[l][unit * kTS + sidx] = H[l + 1][unit * kTS + sidx] > 0.f ? acc[st][i] : 0.f;
+        D[l][unit * kTS + sidx] =
+            unit < Wd ? acc[st][i] * train_act_deriv(act, H[l + 1][unit * kTS + sidx]) : 0.f;
       }
     __syncthreads();
   }
   // weight gradients of this workgroup's 64 samples: dW_l = dZ_l H_l^T
   float* G = a.partial + (int64_t)blockIdx.x * a.n_params;
   for (int l = 0; l <= 4; ++l) {
-    const int nin = l == 0 ? din : 64;
-    const int nout = l == 4 ? m : 64;
+    const int nin = l == 0 ? din : Wd;
+    const int nout = l == 4 ? m : Wd;
     const int n_ob = l == 4 ? 1 : 4, n_ib = l == 0 ? 1 : 4;
     const float* dz = l == 4 ? dY : D[l];
     for (int tile = w; tile < n_ob * n_ib; tile += 4) {
@@ -257,11 +277,12 @@ __global__ __launch_bounds__(256) void k_fwd_bwd(TrainArgs a, int64_t base) {
   for (int q = t; q < 4 * 64 + m; q += 256) {
     const int l = q < 256 ? q / 64 : 4;
     const int o = q < 256 ? q % 64 : q - 256;
+    if (l < 4 && o >= Wd) continue;
     const float* dz = l == 4 ? dY : D[l];
     float sacc = 0.f;
     for (int sidx = 0; sidx < 64; ++sidx) sacc += dz[o * kTS + sidx];
-    const int nin = l == 0 ? din : 64;
-    const int nout = l == 4 ? m : 64;
+    const int nin = l == 0 ? din : Wd;
+    const int nout = l == 4 ? m : Wd;
     G[off[l] + (int64_t)nout * nin + o] = sacc;
   }
   // loss partial: per-wave butterfly, then the four waves in order

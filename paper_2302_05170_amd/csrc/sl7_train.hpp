@@ -17,6 +17,7 @@ struct LabelArgs {
 
 struct TrainArgs {
   int32_t d_in, m;
+  int32_t width, act;    // hidden width (<= 64; units beyond it are held at 0), SL7_RELU / SL7_SOFTPLUS
   int64_t n, batch, n_params;
   const float* X;        // [n x d_in] raw inputs
   const float* Yl;       // [n x m] labels

@@ -52,14 +52,16 @@ struct TrainBufs {
 
 int setup_train(Mlp* H, const float* X_dev, const float* Y_dev, int64_t n, int64_t batch,
                 TrainBufs& B, TrainArgs& a, int64_t steps) {
-  if (H->d.width != kWidth || H->d.depth != SL7_DEPTH || H->d.act != SL7_RELU)
-    return fail(SL7_EUNSUPPORTED, "the trainer is built for 4 x 64 ReLU networks");
+  if (H->d.width > kWidth || H->d.depth != SL7_DEPTH)
+    return fail(SL7_EUNSUPPORTED, "the trainer is built for 4 hidden layers of at most %d units", kWidth);
   if (n < 1) return fail(SL7_EINVAL, "n=%lld must be >= 1", (long long)n);
   if (!X_dev || !Y_dev) return fail(SL7_EINVAL, "X_dev and Y_dev must be non-NULL");
   if (batch < 1 || batch > (int64_t(1) << 20)) return fail(SL7_EINVAL, "batch=%lld out of range", (long long)batch);
   std::memset(&a, 0, sizeof(a));
   a.d_in = H->d.d_in;
   a.m = H->d.m;
+  a.width = H->d.width;
+  a.act = H->d.act;
   a.n = n;
   a.batch = batch;
   a.n_params = (int64_t)H->params.size();

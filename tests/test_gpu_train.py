@@ -96,6 +96,51 @@ def test_training_trajectory_tracks_oracle(S):
     assert hist_g[-1] < 0.5 * hist_g[0]
 
 
+OU_WEIGHTS = os.path.join(ROOT, "tests", "golden", "ou_mlp_5x50_softplus.sl7w")
+
+
+def test_softplus_width50_gradient_matches_oracle(S):
+    """The paper's network shape (4 x 50 Softplus, run padded to 64 units on
+    the trainer's MFMA tiles): the minibatch loss gradient against the
+    oracle's FP64 back-propagation."""
+    Ho = oracle.load_mlp(OU_WEIGHTS)
+    H = S.Mlp.load(OU_WEIGHTS)
+    X = W.ou_features(1024, seed=33).astype(np.float32).astype(np.float64)
+    Y = Ho.forward(X) + 0.01 * np.random.default_rng(1).normal(size=(1024, 5))
+    Y = Y.astype(np.float32).astype(np.float64)
+    loss, g = S.train_grad(H, cuda32(X), cuda32(Y))
+    g = g.double().cpu().numpy()
+    lo, dW, db = oracle.mse_loss_and_grads(Ho, X, Y)
+    ref = oracle.flatten(dW, db)
+    assert g.shape == ref.shape == (Ho.n_params(),)
+    assert abs(loss - lo) <= 1e-4 * lo
+    assert np.max(np.abs(g - ref)) <= 1e-4 * np.max(np.abs(ref))
+
+
+def test_softplus_training_trajectory_tracks_oracle(S):
+    """4 x 50 Softplus from the same Glorot start on the same minibatches:
+    GPU (FP32) and oracle (FP64) Adam losses agree step by step early on,
+    both fall, and the padded units stay out of the parameters."""
+    n = 4096
+    X = W.ou_features(n, seed=42).astype(np.float32).astype(np.float64)
+    Ho_ref = oracle.load_mlp(OU_WEIGHTS)
+    Y = Ho_ref.forward(X).astype(np.float32).astype(np.float64)
+    p0 = W.glorot_params(5, 5, seed=W.TRAIN_SEED, width=W.OU_WIDTH)
+    H0 = oracle.glorot_mlp(5, W.OU_WIDTH, 4, 5, W.OU, W.OU_DOMAIN_LO, W.OU_DOMAIN_HI, p0,
+                           act=oracle.ACT_SOFTPLUS)
+    order = W.minibatch_order(n, 3, seed=6)
+    _, hist_o = oracle.train(H0, X, Y, order, batch=512)
+    H = S.Mlp.create(5, 5, W.OU, p0, H0.in_scale, H0.in_shift, H0.dom_lo, H0.dom_hi,
+                     width=W.OU_WIDTH, act=oracle.ACT_SOFTPLUS)
+    hist_g = S.train(H, cuda32(X), cuda32(Y), epochs=3, batch=512,
+                     order=torch.tensor(order.ravel(), dtype=torch.int32))
+    assert len(hist_g) == len(hist_o) == 24
+    assert np.max(np.abs(hist_g[:8] - hist_o[:8]) / hist_o[:8]) < 1e-3
+    assert np.max(np.abs(hist_g - hist_o) / hist_o) < 5e-2
+    assert hist_g[-1] < 0.5 * hist_g[0]
+    assert H.params().shape == p0.shape and np.all(np.isfinite(H.params()))
+
+
 def test_gpu_trained_network_gain_over_euler(S):
     """Train H on the GPU from the Glorot start (seed 7) on GPU-made labels
     (2^16 rows, 10^4 Euler paths x 100 substeps each), then compare per path
