@@ -298,6 +298,22 @@ def main():
     S.train(Ht, feats, labs, epochs=2)
     t_ep = (time.perf_counter() - t0) / 2
     log(f"labels {t_lab:.2f} s for 2^16 x 10^4 x 100 EM steps; train {t_ep * 1e3:.1f} ms per epoch")
+    # the same for the paper's OU network (4 x 50 Softplus): OU labels, then epochs
+    off_ou = None
+    if os.path.exists(OU_WEIGHTS):
+        feats_o = torch.tensor(W.ou_features(W.N_LABELS), dtype=torch.float32, device="cuda")
+        t0 = time.perf_counter()
+        labs_o = S.labels(W.OU, 5, feats_o, n_paths=W.LABEL_PATHS, substeps=W.LABEL_SUBSTEPS,
+                          seed=W.TRAIN_SEED)
+        torch.cuda.synchronize()
+        t_lab_o = time.perf_counter() - t0
+        Hto = S.Mlp.load(OU_WEIGHTS)
+        S.train(Hto, feats_o, labs_o, epochs=1)
+        t0 = time.perf_counter()
+        S.train(Hto, feats_o, labs_o, epochs=2)
+        t_ep_o = (time.perf_counter() - t0) / 2
+        off_ou = {"labels_s": t_lab_o, "train_ms_per_step": t_ep_o * 1e3 / (W.N_LABELS // W.BATCH)}
+        log(f"OU labels {t_lab_o:.2f} s; train 4x50 softplus {t_ep_o * 1e3:.1f} ms per epoch")
 
     b = res["bf16x3"]
     t_kernel = b["ev_async"]
@@ -344,7 +360,8 @@ def main():
                                               f"T={W.OU_PAPER['T']}, M={W.OU_PAPER['M']}, m=5, "
                                               "MLP 5-50x4-5 Softplus") if ou else None,
         "offline": {"labels_s": t_lab, "label_em_steps": W.N_LABELS * W.LABEL_PATHS * W.LABEL_SUBSTEPS,
-                    "train_ms_per_step": t_ep * 1e3 / (W.N_LABELS // W.BATCH)},
+                    "train_ms_per_step": t_ep * 1e3 / (W.N_LABELS // W.BATCH),
+                    "ou_softplus_4x50": off_ou},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, Ho, c["seed"], args.cpu_paths)
