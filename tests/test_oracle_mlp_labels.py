@@ -1,7 +1,8 @@
 """Pins for the oracle's network maths, training step, labels and CIR law.
 
 * Forward and backward passes of H against torch float64 on the CPU (an
-  independent library implementation of Linear + ReLU and autograd).
+  independent library implementation of Linear + ReLU / Softplus and
+  autograd), also at the paper's width of 50.
 * Adam against torch.optim.Adam.
 * Euler-Maruyama labels (eq. 6.2 with tiny steps, empirical quantiles at
   Phi(x_j)) converge to the closed-form GBM conditional quantiles.
@@ -21,11 +22,11 @@ from scipy import special, stats
 import workloads as W
 
 
-def _net(orc, seed=3, d_in=4, m=5, act=0):
-    params = W.glorot_params(d_in, m, seed=seed)
+def _net(orc, seed=3, d_in=4, m=5, act=0, width=64):
+    params = W.glorot_params(d_in, m, seed=seed, width=width)
     lo = W.GBM_DOMAIN_LO if d_in == 4 else W.CIR_DOMAIN_LO
     hi = W.GBM_DOMAIN_HI if d_in == 4 else W.CIR_DOMAIN_HI
-    H = orc.glorot_mlp(d_in, 64, 4, m, 0, lo, hi, params, act=act)
+    H = orc.glorot_mlp(d_in, width, 4, m, 0, lo, hi, params, act=act)
     rng = np.random.default_rng(seed)
     H.b = [b + rng.normal(scale=0.1, size=b.shape) for b in H.b]
     return H
@@ -40,7 +41,8 @@ def _torch_net(H):
             lin.bias.copy_(torch.from_numpy(bl))
         layers.append(lin)
         if l < H.depth:
-            layers.append(torch.nn.ReLU() if H.act == 0 else torch.nn.Softplus())
+            # no linear cut-over: torch's Softplus returns x above its threshold
+            layers.append(torch.nn.ReLU() if H.act == 0 else torch.nn.Softplus(threshold=1000.0))
     return torch.nn.Sequential(*layers)
 
 
@@ -55,8 +57,9 @@ def test_forward_vs_torch(orc, act):
     assert np.max(np.abs(got_b - ref)) < 1e-13
 
 
-def test_backward_vs_torch_autograd(orc):
-    H = _net(orc)
+@pytest.mark.parametrize("act,width", [(0, 64), (1, 64), (1, 50)])
+def test_backward_vs_torch_autograd(orc, act, width):
+    H = _net(orc, act=act, width=width)
     X = W.gbm_features(300, seed=6)
     Y = np.random.default_rng(2).normal(size=(300, 5))
     loss, dW, db = orc.mse_loss_and_grads(H, X, Y)
