@@ -13,12 +13,15 @@
 * Forward-mode tangents agree with central differences of the oracle.
 """
 import math
+import os
 
 import numpy as np
 import pytest
 from scipy.stats import norm
 
 import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _c0_problem(orc):
@@ -129,6 +132,19 @@ def test_tangents_vs_central_differences_mlp(orc):
         # ReLU kinks make a few paths non-differentiable within +-h
         bad = np.abs(dY[:, p] - fd) > 1e-6 * (1 + np.abs(fd))
         assert bad.mean() < 0.02
+
+
+def test_tangents_vs_central_differences_softplus_ou(orc):
+    """The stored OU network (4 x 50 Softplus, smooth): forward-mode tangents
+    in (Y0, ybar, sigma, lambda) against central differences on every path."""
+    H = orc.load_mlp(os.path.join(ROOT, "tests", "golden", "ou_mlp_5x50_softplus.sl7w"))
+    P = W.OU_PAPER
+    pr = orc.Problem(P["model"], P["theta"], P["Y0"], P["T"], P["M"], P["m"])
+    paths = np.arange(200)
+    _, dY = orc.simulate_tangent(pr, H, 8, paths)
+    for p in range(4):
+        fd = _fd(orc, pr, H, 8, paths, p, 1e-6)
+        assert np.max(np.abs(dY[:, p] - fd)) <= 1e-6 * (1 + np.max(np.abs(fd))), p
 
 
 def test_em_large_step_mean(orc):
