@@ -193,3 +193,20 @@ def test_adjoint_workspace_size(L):
     pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 16, 5, 1000).c()
     assert f(ctypes.byref(pr), L.F64, 0) == 0
     assert f(None, L.F64, 4) == 0
+
+
+def test_batch_tuner_rejects_bad_batches(L):
+    """sl7_autotune_batched checks its batch as sl7_simulate_batched does,
+    before any device work."""
+    import paper_2302_05170_amd as S
+    plan = L.Plan()
+    H = S.Mlp.load(os.path.join(ROOT, "tests", "golden", "cir_mlp_5x64.sl7w"))
+    f = L.lib().sl7_autotune_batched
+    assert f(None, 1, H.handle, L.BF16X3, None, ctypes.byref(plan), None) == L.SL7_EINVAL
+    arr = (L.Problem * 2)(*[S.Problem(W.CIR, (1.0, 0.05, 0.3), 0.05, 1.0, 4, 7, 100).c()] * 2)
+    assert f(arr, 0, H.handle, L.BF16X3, None, ctypes.byref(plan), None) == L.SL7_EINVAL
+    assert f(arr, 2, None, L.BF16X3, None, ctypes.byref(plan), None) == L.SL7_EUNSUPPORTED
+    assert f(arr, 2, H.handle, L.F64, None, ctypes.byref(plan), None) == L.SL7_EUNSUPPORTED
+    assert f(arr, 2, H.handle, L.BF16X3, None, None, None) == L.SL7_EINVAL
+    arr[1].m = 5
+    assert f(arr, 2, H.handle, L.BF16X3, None, ctypes.byref(plan), None) == L.SL7_EINVAL
