@@ -659,6 +659,16 @@ int prepare_instances(const sl7_problem* prs, int n, const Mlp* H, int prec, uin
   return SL7_OK;
 }
 
+// Persistent grid: plan.blocks_per_cu workgroups per CU, but no more than the
+// work items keep busy (each wave takes `grab` 64-path blocks at a time), so
+// a small problem does not start hundreds of waves that only load weights
+// and leave.
+static int persistent_grid(const sl7_plan& plan, int n_cu, int64_t n_items) {
+  const int64_t waves = (n_items + plan.grab - 1) / plan.grab;
+  const int64_t groups = (waves + plan.waves_per_block - 1) / plan.waves_per_block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)plan.blocks_per_cu * n_cu, groups));
+}
+
 // Enqueues the launch sequence: work counter reset, fused kernel, per-instance
 // statistics into ws.stats.  No host synchronisation, no allocation, no
 // memset node (safe to capture into a graph).
@@ -671,14 +681,15 @@ int launch_instances(const SimArgs& a_in, int n, int64_t N0, const Mlp* H, int p
   if (is_pwl(prec)) {
     e = launch_zero_u64(a.counter, 1, stream);
     if (e != hipSuccess) return hip_fail(e, "zero counter");
-    e = launch_sim_pwl(prec, a, plan.blocks_per_cu * ws.n_cu, plan.waves_per_block, stream);
+    e = launch_sim_pwl(prec, a, persistent_grid(plan, ws.n_cu, a.n_items), plan.waves_per_block,
+                       stream);
     if (e != hipSuccess) return hip_fail(e, "launch piecewise-linear kernel");
   } else if (mfma) {
     a.wpack = H->pack[prec]->p;
     e = launch_zero_u64(a.counter, 1, stream);
     if (e != hipSuccess) return hip_fail(e, "zero counter");
-    const int grid = plan.blocks_per_cu * ws.n_cu;
-    e = launch_sim_mfma(prec, H->d.act, a, grid, plan.waves_per_block, stream);
+    e = launch_sim_mfma(prec, H->d.act, a, persistent_grid(plan, ws.n_cu, a.n_items),
+                        plan.waves_per_block, stream);
     if (e != hipSuccess) return hip_fail(e, "launch fused MFMA kernel");
   } else {
     if (n != 1) return fail(SL7_EUNSUPPORTED, "batched launches need a network in F32/BF16/F16");
