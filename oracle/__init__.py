@@ -26,11 +26,10 @@ path at a time); this module adds the node computation, the batched network
 maths used for training checks, the estimators, the weight-file reader and a
 thread pool over independent paths.
 
-Parity status: every routine here is pinned by closed forms, library routines
-or invariants in ``tests/test_oracle_*.py`` except the Philox generator, whose
-bit stream has no external known-answer vectors in this repository ("parity
-unpinned" against an external reference; it is pinned structurally and
-statistically instead).
+Parity status: every routine here is pinned by closed forms, library routines,
+published values or invariants in ``tests/test_oracle_*.py``; the Philox
+generator by the known-answer vectors published with its reference
+implementation (``tests/golden/philox4x32_10_kat.txt``).
 """
 from __future__ import annotations
 
