@@ -210,3 +210,17 @@ def test_batch_tuner_rejects_bad_batches(L):
     assert f(arr, 2, H.handle, L.BF16X3, None, None, None) == L.SL7_EINVAL
     arr[1].m = 5
     assert f(arr, 2, H.handle, L.BF16X3, None, ctypes.byref(plan), None) == L.SL7_EINVAL
+
+
+def test_binding_fails_loudly_without_the_library(L, monkeypatch, tmp_path):
+    """With libsl7.so absent the binding raises on first use: there is no
+    other implementation behind it to fall back to."""
+    import paper_2302_05170_amd as S
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "libsl7.so"))
+    monkeypatch.setattr(L, "_lib", None)
+    with pytest.raises(RuntimeError, match="is missing"):
+        L.lib()
+    with pytest.raises(RuntimeError, match="is missing"):
+        S.Mlp.load(WEIGHTS)
+    with pytest.raises(RuntimeError, match="is missing"):
+        S.gh_nodes(5)
