@@ -112,7 +112,9 @@ typedef struct {
 
 /* One simulation instance (Algorithm I, online stage).  dt = T / M,
  * t_i = i T / M.  Paths path_offset .. path_offset + N - 1 (global indices,
- * used as the Philox counter).  instance becomes the low 24 bits of the tag. */
+ * used as the Philox counter; path_offset >= 0, path_offset + N <= 2^63 - 1,
+ * 1 <= N <= 2^40, else SL7_EINVAL).  instance becomes the low 24 bits of the
+ * tag. */
 typedef struct {
   int32_t model, m, M, reserved0;
   int64_t N;

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -457,6 +458,8 @@ int check_problem(const sl7_problem* pr, const Mlp* H, int prec, const char* nam
   if (pr->N < 1) return fail(SL7_EINVAL, "%s.N=%lld must be >= 1", name, (long long)pr->N);
   if (pr->N > (int64_t(1) << 40)) return fail(SL7_EINVAL, "%s.N=%lld too large", name, (long long)pr->N);
   if (pr->path_offset < 0) return fail(SL7_EINVAL, "%s.path_offset must be >= 0", name);
+  if (pr->path_offset > INT64_MAX - pr->N)
+    return fail(SL7_EINVAL, "%s.path_offset + N exceeds the 63-bit path index", name);
   if (pr->instance > 0xFFFFFFu) return fail(SL7_EINVAL, "%s.instance must fit 24 bits", name);
   if (!(pr->T > 0.0) || !std::isfinite(pr->T)) return fail(SL7_EINVAL, "%s.T must be finite and > 0", name);
   if (!std::isfinite(pr->Y0)) return fail(SL7_EINVAL, "%s.Y0 not finite", name);

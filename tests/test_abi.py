@@ -119,6 +119,8 @@ def _sim_rc(L, H=None, prec=1, **kw):
     (dict(Y0=float("inf")), "Y0"), (dict(model=7), "model"),
     (dict(model=W.CIR, theta=(1.0, 0.05, 0.2), Y0=-0.1), "Y0"),
     (dict(model=W.OU, theta=(0.5, 0.3, 0.0)), "lambda"),
+    (dict(path_offset=-1), "path_offset"), (dict(path_offset=2 ** 63 - 100), "63-bit"),
+    (dict(N=2 ** 40 + 1), "too large"),
 ])
 def test_simulate_rejects_bad_problems(L, kw, needle):
     rc, msg = _sim_rc(L, **kw)

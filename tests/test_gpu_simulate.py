@@ -214,6 +214,26 @@ def test_path_offset_shards_compose(S, H):
     assert np.array_equal(yp, y[1500:2500])
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "f16x3", "pwl32", "pwl64"])
+def test_path_indices_beyond_32_bits(S, H, Ho, prec):
+    """Global path indices fill both 32-bit words of the Philox counter: a
+    shard straddling 2^32 and the last shard of the 63-bit index range match
+    the oracle at the same global indices."""
+    c = W.CONFIGS["gbm_mlp_2p22x16"]
+    tol = {"pwl32": TOL["f32"], "pwl64": TOL["f64"]}.get(prec, TOL.get(prec))
+    N = 300
+    for off in (2 ** 32 - 150, 2 ** 63 - 1 - N):
+        pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 5, c["m"], N, K=c["K"],
+                       path_offset=off)
+        ref = orc(pr, Ho, 13, off + np.arange(N, dtype=np.int64))
+        st, y = gpu_yt(S, pr, H, prec, 13)
+        assert st["n"] == N
+        assert rel(y, ref).max() <= tol, (prec, off)
+    # the two shards differ from the first paths of the stream
+    lo = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 5, c["m"], N, K=c["K"])
+    assert not np.array_equal(gpu_yt(S, lo, H, prec, 13)[1], y)
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16", "bf16x3", "f16x3"])
 def test_eval_H_matches_oracle_forward(S, H, Ho, prec):
     x = W.gbm_features(5000, seed=99)
