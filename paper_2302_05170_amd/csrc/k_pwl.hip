@@ -8,8 +8,11 @@
 //   piece    p = number of breakpoints <= Y, from a uniform grid over the
 //            breakpoints (one cell load) and a short scan either way
 //   H        y_j = c_j + a_j (Y - o)              (m FMAs, the piece's record)
-//   g_m(X)   barycentric interpolation (weights multiplied through by the
-//            node polynomial: one division per step, exact at the nodes)
+//   g_m(X)   FP64: barycentric interpolation (weights multiplied through by
+//            the node polynomial: one division per step, exact at the nodes);
+//            FP32: the same polynomial in monomial form, whose coefficients
+//            are affine in Y on a piece and come precomputed in the record:
+//            q_k = c_k + a_k (Y - o), Horner in X (2m - 1 FMAs, no division)
 // and the same Philox normals, clamping, domain counting and fixed-order
 // 64-path block sums as the other simulation kernels.  Work is 64-path
 // blocks of all instances from the shared work queue.
@@ -97,12 +100,20 @@ __device__ __forceinline__ void pwl_block(const SimArgs& a, const InstDev& I, in
       if (i0 + u < M) {
         if (Y < dlo || Y > dhi) ++ood;
         const T* __restrict__ rec = rec0 + (int64_t)pwl_piece<T>(base, I, Y) * kPwlStride;
-        T sl[MM], va[MM], y[MM];
+        T sl[MM], va[MM];
         load_record<T, MM>(rec, sl, va);
         const T dY = Y - rec[2 * kMaxM];
+        if constexpr (F64) {
+          T y[MM];
 #pragma unroll
-        for (int j = 0; j < MM; ++j) y[j] = fma(sl[j], dY, va[j]);
-        Y = interp_lane<T, MM>(xs, ls, y, xq[u]);
+          for (int j = 0; j < MM; ++j) y[j] = fma(sl[j], dY, va[j]);
+          Y = interp_lane<T, MM>(xs, ls, y, xq[u]);
+        } else {
+          T g = fma(sl[MM - 1], dY, va[MM - 1]);
+#pragma unroll
+          for (int k = MM - 2; k >= 0; --k) g = fma(g, xq[u], fma(sl[k], dY, va[k]));
+          Y = g;
+        }
         if (clamp && Y < T(0)) { Y = T(0); ++clamped; }
       }
     }

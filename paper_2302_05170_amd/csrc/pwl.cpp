@@ -310,11 +310,43 @@ static int pwl_lookup_all(const sl7_problem* prs, int n, Mlp* H, bool with_theta
   return SL7_OK;
 }
 
+// Monomial coefficients of the Lagrange basis through the Gauss-Hermite nodes
+// of N(0,1): l_j(X) = sum_k C[j m + k] X^k, from the product
+// prod_{i != j} (X - x_i) / (x_j - x_i) expanded one factor at a time (FP64).
+static int lagrange_monomial(int m, std::vector<double>& C) {
+  double x[kMaxM], w[kMaxM];
+  const int rc = gh_nodes(m, x, w);
+  if (rc != SL7_OK) return rc;
+  C.assign((size_t)m * m, 0.0);
+  for (int j = 0; j < m; ++j) {
+    double* c = &C[(size_t)j * m];
+    c[0] = 1.0;
+    int deg = 0;
+    for (int i = 0; i < m; ++i) {
+      if (i == j) continue;
+      const double s = 1.0 / (x[j] - x[i]);
+      for (int k = deg + 1; k >= 0; --k)
+        c[k] = ((k > 0 ? c[k - 1] : 0.0) - x[i] * c[k]) * s;
+      ++deg;
+    }
+  }
+  return SL7_OK;
+}
+
 // One instance's tables in the lane type, laid out as on the device (piece
-// records, breakpoints, grid cells; offsets from the blob's start).
+// records, breakpoints, grid cells; offsets from the blob's start).  In FP32
+// simulation records the slope and value slots hold instead the monomial
+// coefficients of the interpolant through the piece's collocation values:
+// on the piece, g_m(X) = sum_k (c_k + a_k (Y - o)) X^k.
 static int serialize(const PwlPieces& P, bool f64, bool with_theta, PwlBlob& B) {
   const size_t el = f64 ? sizeof(double) : sizeof(float);
   const int stride = with_theta ? kPwlAdjStride : kPwlStride;
+  const bool monomial = !f64 && !with_theta;
+  std::vector<double> C;
+  if (monomial) {
+    const int rc = lagrange_monomial(P.m, C);
+    if (rc != SL7_OK) return rc;
+  }
   grid_shape(P, B.cells, B.g0, B.ih);
   B.P = P.P;
   B.rec = 0;
@@ -336,7 +368,14 @@ static int serialize(const PwlPieces& P, bool f64, bool with_theta, PwlBlob& B) 
         }
     }
     for (int j = 0; j < P.m; ++j) {
-      const double a = P.a[(size_t)p * P.m + j], c = P.c[(size_t)p * P.m + j];
+      double a = P.a[(size_t)p * P.m + j], c = P.c[(size_t)p * P.m + j];
+      if (monomial) {  // coefficient of X^j: sum_i C[i][j] times slope / value i
+        a = c = 0.0;
+        for (int i = 0; i < P.m; ++i) {
+          a += C[(size_t)i * P.m + j] * P.a[(size_t)p * P.m + i];
+          c += C[(size_t)i * P.m + j] * P.c[(size_t)p * P.m + i];
+        }
+      }
       if (f64) {
         put(buf, r + j * el, a);
         put(buf, r + (kMaxM + j) * el, c);
