@@ -99,19 +99,30 @@ __device__ __forceinline__ void pwl_block(const SimArgs& a, const InstDev& I, in
     for (int u = 0; u < 4; ++u) {
       if (i0 + u < M) {
         if (Y < dlo || Y > dhi) ++ood;
-        const T* __restrict__ rec = rec0 + (int64_t)pwl_piece<T>(base, I, Y) * kPwlStride;
-        T sl[MM], va[MM];
-        load_record<T, MM>(rec, sl, va);
-        const T dY = Y - rec[2 * kMaxM];
+        const int piece = pwl_piece<T>(base, I, Y);
         if constexpr (F64) {
-          T y[MM];
+          const T* __restrict__ rec = rec0 + (int64_t)piece * kPwlStride;
+          T sl[MM], va[MM], y[MM];
+          load_record<T, MM>(rec, sl, va);
+          const T dY = Y - rec[2 * kMaxM];
 #pragma unroll
           for (int j = 0; j < MM; ++j) y[j] = fma(sl[j], dY, va[j]);
           Y = interp_lane<T, MM>(xs, ls, y, xq[u]);
         } else {
-          T g = fma(sl[MM - 1], dY, va[MM - 1]);
+          // packed record: (a_k, c_k) pairs, then the anchor, in NQ 16-byte loads
+          typedef float f4 __attribute__((ext_vector_type(4)));
+          constexpr int NQ = (2 * MM + 1 + 3) / 4;
+          const f4* __restrict__ rec = (const f4*)(rec0 + (int64_t)piece * pwl32_stride(MM));
+          float r[4 * NQ];
 #pragma unroll
-          for (int k = MM - 2; k >= 0; --k) g = fma(g, xq[u], fma(sl[k], dY, va[k]));
+          for (int q = 0; q < NQ; ++q) {
+            const f4 v = rec[q];
+            r[4 * q] = v[0]; r[4 * q + 1] = v[1]; r[4 * q + 2] = v[2]; r[4 * q + 3] = v[3];
+          }
+          const float dY = Y - r[2 * MM];
+          float g = fma(r[2 * MM - 2], dY, r[2 * MM - 1]);
+#pragma unroll
+          for (int k = MM - 2; k >= 0; --k) g = fma(g, xq[u], fma(r[2 * k], dY, r[2 * k + 1]));
           Y = g;
         }
         if (clamp && Y < T(0)) { Y = T(0); ++clamped; }

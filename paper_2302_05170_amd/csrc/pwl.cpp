@@ -334,14 +334,15 @@ static int lagrange_monomial(int m, std::vector<double>& C) {
 }
 
 // One instance's tables in the lane type, laid out as on the device (piece
-// records, breakpoints, grid cells; offsets from the blob's start).  In FP32
-// simulation records the slope and value slots hold instead the monomial
-// coefficients of the interpolant through the piece's collocation values:
-// on the piece, g_m(X) = sum_k (c_k + a_k (Y - o)) X^k.
+// records, breakpoints, grid cells; offsets from the blob's start).  FP32
+// simulation records are packed (pwl32_stride): the interpolant's monomial
+// coefficients as pairs (a_k, c_k), then the anchor o; on the piece
+// g_m(X) = sum_k (c_k + a_k (Y - o)) X^k.  The other records hold the
+// collocation values' slopes a[kMaxM], values c[kMaxM] and anchor o.
 static int serialize(const PwlPieces& P, bool f64, bool with_theta, PwlBlob& B) {
   const size_t el = f64 ? sizeof(double) : sizeof(float);
-  const int stride = with_theta ? kPwlAdjStride : kPwlStride;
   const bool monomial = !f64 && !with_theta;
+  const int stride = with_theta ? kPwlAdjStride : monomial ? pwl32_stride(P.m) : kPwlStride;
   std::vector<double> C;
   if (monomial) {
     const int rc = lagrange_monomial(P.m, C);
@@ -356,6 +357,21 @@ static int serialize(const PwlPieces& P, bool f64, bool with_theta, PwlBlob& B) 
   buf.assign(align256(B.grid + (size_t)B.cells * 16), 0);
   for (int p = 0; p < P.P; ++p) {
     const size_t r = B.rec + (size_t)p * stride * el;
+    const double* a = &P.a[(size_t)p * P.m];
+    const double* c = &P.c[(size_t)p * P.m];
+    if (monomial) {
+      for (int k = 0; k < P.m; ++k) {  // coefficient of X^k: sum_i C[i][k] times slope / value i
+        double ak = 0.0, ck = 0.0;
+        for (int i = 0; i < P.m; ++i) {
+          ak += C[(size_t)i * P.m + k] * a[i];
+          ck += C[(size_t)i * P.m + k] * c[i];
+        }
+        put(buf, r + (2 * k) * el, (float)ak);
+        put(buf, r + (2 * k + 1) * el, (float)ck);
+      }
+      put(buf, r + 2 * P.m * el, (float)P.o[p]);
+      continue;
+    }
     if (with_theta) {
       for (int k = 0; k < P.n_theta; ++k)
         for (int j = 0; j < P.m; ++j) {
@@ -368,20 +384,12 @@ static int serialize(const PwlPieces& P, bool f64, bool with_theta, PwlBlob& B) 
         }
     }
     for (int j = 0; j < P.m; ++j) {
-      double a = P.a[(size_t)p * P.m + j], c = P.c[(size_t)p * P.m + j];
-      if (monomial) {  // coefficient of X^j: sum_i C[i][j] times slope / value i
-        a = c = 0.0;
-        for (int i = 0; i < P.m; ++i) {
-          a += C[(size_t)i * P.m + j] * P.a[(size_t)p * P.m + i];
-          c += C[(size_t)i * P.m + j] * P.c[(size_t)p * P.m + i];
-        }
-      }
       if (f64) {
-        put(buf, r + j * el, a);
-        put(buf, r + (kMaxM + j) * el, c);
+        put(buf, r + j * el, a[j]);
+        put(buf, r + (kMaxM + j) * el, c[j]);
       } else {
-        put(buf, r + j * el, (float)a);
-        put(buf, r + (kMaxM + j) * el, (float)c);
+        put(buf, r + j * el, (float)a[j]);
+        put(buf, r + (kMaxM + j) * el, (float)c[j]);
       }
     }
     if (f64) put(buf, r + 2 * kMaxM * el, P.o[p]); else put(buf, r + 2 * kMaxM * el, (float)P.o[p]);

@@ -9,6 +9,11 @@
 
 namespace sl7 {
 
+// Entries per FP32 simulation piece record: m pairs (a_k, c_k) of monomial
+// coefficients, then the anchor, padded to 64 bytes (one cache line) when
+// that fits, else to 128.
+__host__ __device__ constexpr int pwl32_stride(int m) { return 2 * m + 1 <= 16 ? 16 : 32; }
+
 // Cell of the uniform lookup grid for Y, computed identically on the host
 // (the host derives each cell's exact range of Y from this same arithmetic).
 template <typename T>
