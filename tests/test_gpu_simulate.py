@@ -234,6 +234,41 @@ def test_path_indices_beyond_32_bits(S, H, Ho, prec):
     assert not np.array_equal(gpu_yt(S, lo, H, prec, 13)[1], y)
 
 
+def network_with_m_outputs(S, H, m2, path):
+    """The stored GBM network with its head re-interpolated onto the m2
+    Gauss-Hermite nodes: head row k becomes sum_j l_j(x'_k) row_j (Lagrange
+    basis on the 5 nodes), so the outputs stay collocation-point shaped."""
+    d = H.desc()
+    x5, _ = oracle.gh_nodes(d.m)
+    x2, _ = oracle.gh_nodes(m2)
+    Lm = np.array([[np.prod([(xk - x5[i]) / (x5[j] - x5[i]) for i in range(d.m) if i != j])
+                    for j in range(d.m)] for xk in x2])
+    p = H.params().astype(np.float64)
+    nb, nw = d.m, d.m * d.width
+    Wh, bh = p[-nb - nw:-nb].reshape(d.m, d.width), p[-nb:]
+    p2 = np.concatenate([p[:-nb - nw], (Lm @ Wh).ravel(), Lm @ bh]).astype(np.float32)
+    H2 = S.Mlp.create(d.d_in, m2, d.model, p2, list(d.in_scale)[:d.d_in], list(d.in_shift)[:d.d_in],
+                      list(d.dom_lo)[:d.d_in], list(d.dom_hi)[:d.d_in], width=d.width)
+    H2.save(path)
+    return H2, oracle.load_mlp(path)
+
+
+@pytest.mark.parametrize("m2", [2, 3, 4, 6, 8])
+def test_every_node_count_in_every_network_mode(S, H, m2, tmp_path):
+    """Each kernel is specialised on m: networks with 2..8 outputs (other than
+    the stored 5 and 7) against the oracle in every network mode."""
+    H2, Ho2 = network_with_m_outputs(S, H, m2, str(tmp_path / f"gbm_m{m2}.sl7w"))
+    c = W.CONFIGS["gbm_mlp_2p22x16"]
+    pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 7, m2, 1000, K=c["K"])
+    ref = orc(pr, Ho2, 17, np.arange(pr.N))
+    assert np.all(np.isfinite(ref)) and ref.std() > 0.05
+    for prec in ("f64", "f32", "bf16x3", "f16x3", "pwl32", "pwl64"):
+        tol = {"pwl32": TOL["f32"], "pwl64": TOL["f64"]}.get(prec, TOL.get(prec))
+        st, y = gpu_yt(S, pr, H2, prec, 17)
+        assert st["n"] == pr.N
+        assert rel(y, ref).max() <= tol, (m2, prec, rel(y, ref).max())
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f16", "bf16x3", "f16x3"])
 def test_eval_H_matches_oracle_forward(S, H, Ho, prec):
     x = W.gbm_features(5000, seed=99)
