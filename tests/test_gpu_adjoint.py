@@ -15,6 +15,7 @@ from scipy.stats import norm
 
 import oracle
 import workloads as W
+from nets import network_with_m_outputs
 
 pytestmark = pytest.mark.gpu
 
@@ -244,3 +245,17 @@ def test_piecewise_linear_adjoint_on_cir(S):
     a, b = a.cpu().numpy(), b.cpu().numpy()
     scale = 1 + np.max(np.abs(b), axis=0)
     assert np.all(np.max(np.abs(a - b), axis=0) / scale <= 1e-10)
+
+
+@pytest.mark.parametrize("m2", [3, 8])
+def test_adjoint_other_node_counts(S, H, m2, tmp_path):
+    """Networks with 3 and 8 outputs (the stored head re-interpolated onto
+    the other node sets): network and piecewise-linear reverse sweeps against
+    the oracle's per-path tangents, FP64."""
+    H2, Ho2 = network_with_m_outputs(S, H, m2, str(tmp_path / f"gbm_m{m2}.sl7w"))
+    pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 9, m2, 1500, K=1.0)
+    f, df = oracle_pathwise(pr, Ho2, 23, 1, pr.N)
+    for prec in ("f64", "pwl64"):
+        g, pp = S.adjoint(pr, H2, prec=prec, seed=23, payoff=1, ckpt_every=4, per_path=True)
+        err = check_pathwise(pp.cpu().numpy(), f, df, g)
+        print(m2, prec, "max pathwise gradient error", err)
