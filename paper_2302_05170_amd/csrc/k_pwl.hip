@@ -7,12 +7,14 @@
 // all M steps (Algorithm I, steps 3-6):
 //   piece    p = number of breakpoints <= Y, from a uniform grid over the
 //            breakpoints (one cell load) and a short scan either way
-//   H        y_j = c_j + a_j (Y - o)              (m FMAs, the piece's record)
-//   g_m(X)   FP64: barycentric interpolation (weights multiplied through by
-//            the node polynomial: one division per step, exact at the nodes);
-//            FP32: the same polynomial in monomial form, whose coefficients
-//            are affine in Y on a piece and come precomputed in the record:
-//            q_k = c_k + a_k (Y - o), Horner in X (2m - 1 FMAs, no division)
+//   FP64     H: y_j = c_j + a_j (Y - o) (m FMAs from the piece's record);
+//            g_m(X) by barycentric interpolation (weights multiplied through
+//            by the node polynomial: one division per step, exact at the
+//            nodes)
+//   FP32     H and g_m together: the interpolating polynomial's monomial
+//            coefficients are affine in Y on a piece and come precomputed in
+//            the packed record: q_k = c_k + a_k (Y - o), Horner in X
+//            (2m - 1 FMAs, no division)
 // and the same Philox normals, clamping, domain counting and fixed-order
 // 64-path block sums as the other simulation kernels.  Work is 64-path
 // blocks of all instances from the shared work queue.
