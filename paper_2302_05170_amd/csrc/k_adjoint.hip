@@ -17,6 +17,7 @@
 // workgroup; block sums in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include "block_grid.hpp"
 #include "device_common.hpp"
 #include "net_lane.hpp"
 #include "pwl_device.hpp"
@@ -180,8 +181,10 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, 64),
   T* ybuf = (T*)lds_adj + (is_net(MODE) ? kLaneStageRows * 64 : 0) + lane;
   uint32_t* cbuf = (uint32_t*)(ybuf - lane + k * 64) + lane;
   // evaluation state of the segment's steps, [ckpt][NW][64] per block
-  uint32_t* st = a.state_buf + (int64_t)blockIdx.x * k * NW * 64 + lane;
-  const int64_t p = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t blk = block_index();
+  if (blk * 64 >= I.N) return;
+  uint32_t* st = a.state_buf + blk * k * NW * 64 + lane;
+  const int64_t p = blk * 64 + lane;
   const bool valid = p < I.N;
   const int64_t gp = I.path_offset + p;
   const uint32_t tag = (uint32_t)I.tag;
@@ -260,7 +263,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, 64),
       P.s[t] = s[t];
       P.s2[t] = s2[t];
     }
-    a.partials[blockIdx.x] = P;
+    a.partials[blk] = P;
   }
 }
 
@@ -315,7 +318,7 @@ static hipError_t launch_one(const AdjArgs& a, int64_t n_blocks, size_t lds, hip
   hipError_t e = hipFuncSetAttribute((const void*)k_adjoint<T, MODE>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_adjoint<T, MODE>), dim3((unsigned)n_blocks), dim3(64), lds, s, a);
+  hipLaunchKernelGGL((k_adjoint<T, MODE>), block_grid(n_blocks), dim3(64), lds, s, a);
   return hipGetLastError();
 }
 

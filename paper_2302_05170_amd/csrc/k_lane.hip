@@ -10,6 +10,7 @@
 // section, second form, exact-node branch).
 #include <hip/hip_runtime.h>
 
+#include "block_grid.hpp"
 #include "device_common.hpp"
 #include "net_lane.hpp"
 
@@ -51,7 +52,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, 64),
   extern __shared__ double lds_h[];
   const InstDev& I = a.inst[0];
   const int lane = threadIdx.x;
-  const int64_t blk = blockIdx.x;
+  const int64_t blk = block_index();
+  if (blk * 64 >= I.N) return;
   const int64_t p = blk * 64 + lane;
   const bool valid = p < I.N;
   const int64_t gp = I.path_offset + p;
@@ -103,7 +105,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, 64),
 hipError_t launch_sim_lane(int prec, int use_net, int act, const SimArgs& a, int64_t n_blocks,
                            hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
-  dim3 grid((unsigned)n_blocks), block(64);
+  const dim3 grid = block_grid(n_blocks), block(64);
   if (prec == SL7_F64) {
     if (use_net) {
       const size_t lds = kLaneStageRows * 64 * sizeof(double);
@@ -262,7 +264,8 @@ __global__ __launch_bounds__(64) void k_eval_lane(const double* __restrict__ net
                                                   int64_t B, float* __restrict__ out) {
   extern __shared__ double lds_h[];
   const int lane = threadIdx.x;
-  const int64_t row = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t row = block_index() * 64 + lane;
+  if (row - lane >= B) return;
   const bool valid = row < B;
   double h0[kMaxDinLane];
   for (int k = 0; k < kMaxDinLane; ++k) h0[k] = 0.0;
@@ -307,7 +310,7 @@ hipError_t launch_eval_lane(const double* net, const double* w0full, int d_in, i
                             const float* in, int64_t B, float* out, hipStream_t s) {
   if (B <= 0) return hipSuccess;
   const size_t lds = 2 * 64 * 64 * sizeof(double);
-  hipLaunchKernelGGL(k_eval_lane, dim3((unsigned)((B + 63) / 64)), dim3(64), lds, s, net, w0full,
+  hipLaunchKernelGGL(k_eval_lane, block_grid((B + 63) / 64), dim3(64), lds, s, net, w0full,
                      d_in, m, act, in, B, out);
   return hipGetLastError();
 }

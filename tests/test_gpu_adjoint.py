@@ -259,3 +259,18 @@ def test_adjoint_other_node_counts(S, H, m2, tmp_path):
         g, pp = S.adjoint(pr, H2, prec=prec, seed=23, payoff=1, ckpt_every=4, per_path=True)
         err = check_pathwise(pp.cpu().numpy(), f, df, g)
         print(m2, prec, "max pathwise gradient error", err)
+
+
+def test_adjoint_second_grid_row(S):
+    """Just past 2^16 blocks (N = 2^22 + 1000) the adjoint's launch grid gains
+    a second row: analytic map, FP64, sampled paths either side of the row
+    boundary and at the end against the oracle's tangents."""
+    N = 2 ** 22 + 1000
+    pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 3, 5, N, K=1.0)
+    g, pp = S.adjoint(pr, None, prec="f64", seed=31, payoff=0, ckpt_every=2, per_path=True)
+    idx = np.concatenate([np.arange(64), 2 ** 22 + np.arange(-64, 64), N - 64 + np.arange(64)])
+    pp = pp[torch.from_numpy(idx).cuda()].cpu().numpy()
+    opr = oracle.Problem(pr.model, pr.theta, pr.Y0, pr.T, pr.M, pr.m, pr.instance)
+    f, df = oracle.simulate_tangent(opr, None, 31, idx)
+    assert np.max(np.abs(pp[:, 0] - f)) <= 1e-12 * (1 + np.max(np.abs(f)))
+    assert np.max(np.abs(pp[:, 1:] - df) / (1 + np.abs(df))) <= 1e-10

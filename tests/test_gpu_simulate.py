@@ -235,6 +235,54 @@ def test_path_indices_beyond_32_bits(S, H, Ho, prec):
     assert not np.array_equal(gpu_yt(S, lo, H, prec, 13)[1], y)
 
 
+def test_per_lane_kernel_beyond_2p32_paths(S):
+    """The per-lane kernel (analytic map, FP32) at N = 2^32 + 1000 paths, one
+    step: its blocks span both dimensions of the launch grid.  Paths sampled
+    at the start, around 2^31 and 2^32 and at the end match the oracle, and
+    every path is counted."""
+    N = 2 ** 32 + 1000
+    pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 0.25, 1, 5, N, K=1.0)
+    st, yt = S.simulate(pr, None, prec="f32", seed=4, want_yt=True)
+    torch.cuda.synchronize()
+    idx = np.concatenate([np.arange(100), 2 ** 31 + np.arange(-50, 50), 2 ** 32 + np.arange(-50, 50),
+                          N - 100 + np.arange(100)]).astype(np.int64)
+    got = yt[torch.from_numpy(idx).cuda()].double().cpu().numpy()
+    del yt
+    ref = orc(pr, None, 4, idx)
+    assert st["n"] == N
+    assert rel(got, ref).max() <= TOL["f32"]
+    # one step of the analytic map: E[Y_1] = Y0 sum_j w_j y_j exactly
+    assert abs(st["mean"][0] - 1.0 * np.exp(0.1 * 0.25)) <= 5 * st["se"][0]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_per_lane_kernel_second_grid_row(S, H, Ho, prec):
+    """Just past 2^16 blocks the per-lane launch grid gains a second row
+    (N = 2^22 + 1000): sampled paths either side of the row boundary and at
+    the end against the oracle."""
+    N = 2 ** 22 + 1000
+    c = W.CONFIGS["gbm_mlp_2p22x16"]
+    pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 2, c["m"], N, K=c["K"])
+    net, neto = (H, Ho) if prec == "f64" else (None, None)
+    st, yt = S.simulate(pr, net, prec=prec, seed=6, want_yt=True)
+    torch.cuda.synchronize()
+    idx = np.concatenate([np.arange(64), 2 ** 22 + np.arange(-64, 64), N - 64 + np.arange(64)])
+    got = yt.double().cpu().numpy()[idx]
+    assert st["n"] == N
+    assert rel(got, orc(pr, neto, 6, idx)).max() <= TOL[prec]
+
+
+def test_eval_H_f64_second_grid_row(S, H, Ho):
+    B = 2 ** 22 + 100
+    x = W.gbm_features(B, seed=12).astype(np.float32)
+    out = S.eval_H(H, torch.from_numpy(x).cuda(), prec="f64")
+    torch.cuda.synchronize()
+    idx = np.concatenate([np.arange(32), 2 ** 22 + np.arange(-32, 32), B - 32 + np.arange(32)])
+    ref = Ho.forward(x[idx].astype(np.float64))
+    got = out.double().cpu().numpy()[idx]
+    assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 0.1)) <= 1.2e-7
+
+
 @pytest.mark.parametrize("m2", [2, 3, 4, 6, 8])
 def test_every_node_count_in_every_network_mode(S, H, m2, tmp_path):
     """Each kernel is specialised on m: networks with 2..8 outputs (other than
