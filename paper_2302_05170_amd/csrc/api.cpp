@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -244,6 +245,11 @@ float Mlp::b(int l, int o) const {
   return o < out ? params[b_off[l] + o] : 0.f;
 }
 
+uint64_t next_mlp_version() {
+  static std::atomic<uint64_t> next{1};
+  return next.fetch_add(1);
+}
+
 void Mlp::drop_device() {
   for (auto& p : pack) p.reset();
   net64.reset();
@@ -256,7 +262,7 @@ void Mlp::drop_device() {
   c0n.reset();
   device = -1;
   pwl_cache.clear();
-  ++version;
+  version = next_mlp_version();
 }
 
 static uint16_t to_bf16_bits(float f) {

@@ -34,6 +34,7 @@ uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
 // A captured launch sequence with buffers of its own, so replays need no
 // upload and are not disturbed by other calls on the device.
 struct GraphEntry {
+  std::string key;  // everything the captured nodes depend on (see graph_key)
   Workspace ws;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -103,29 +104,36 @@ extern "C" int sl7_simulate_batched(const sl7_problem* prs, int n, const sl7_mlp
     if (rc) return rc;
     return fetch_stats(ws, n, stats_host, s);
   }
-  // graph path: key on everything the captured nodes depend on
-  uint64_t key = fnv1a(p.data(), sizeof(sl7_problem) * n);
-  key = fnv1a(&plan, sizeof(plan), key);
-  key = fnv1a(&seed, sizeof(seed), key);
-  key = fnv1a(&prec, sizeof(prec), key);
-  key = fnv1a(&dev, sizeof(dev), key);
-  if (is_pwl(prec)) {
-    // the tables are built into the entry's own workspace from the weights
-    // of this version of H
-    const void* hp = H;
-    key = fnv1a(&hp, sizeof(hp), key);
-    key = fnv1a(&H->version, sizeof(uint64_t), key);
-  } else {
+  // graph path: the entry is found by a hash of everything the captured
+  // nodes depend on (the problems, plan, seed, precision, device, the
+  // network's version, which changes with its parameters and is unique in
+  // the process, and its device weights) and used only if all of it matches
+  std::string full;
+  auto add = [&full](const void* b, size_t nb) { full.append((const char*)b, nb); };
+  add(p.data(), sizeof(sl7_problem) * n);
+  add(&plan, sizeof(plan));
+  add(&seed, sizeof(seed));
+  add(&prec, sizeof(prec));
+  add(&dev, sizeof(dev));
+  add(&H->version, sizeof(H->version));
+  if (!is_pwl(prec)) {
     const void* wp = H->pack[prec]->p;
-    key = fnv1a(&wp, sizeof(wp), key);
-    key = fnv1a(&H->pack[prec]->generation, sizeof(uint64_t), key);
+    add(&wp, sizeof(wp));
+    add(&H->pack[prec]->generation, sizeof(uint64_t));
   }
+  const uint64_t key = fnv1a(full.data(), full.size());
   GraphCache& gc = graph_cache();
   std::lock_guard<std::mutex> lk(gc.mu);
   auto it = gc.entries.find(key);
+  if (it != gc.entries.end() && it->second->key != full) {  // a hash collision: rebuild
+    gc.entries.erase(it);
+    gc.lru.erase(std::remove(gc.lru.begin(), gc.lru.end(), key), gc.lru.end());
+    it = gc.entries.end();
+  }
   GraphEntry* E = nullptr;
   if (it == gc.entries.end()) {
     std::unique_ptr<GraphEntry> ne(new GraphEntry());
+    ne->key = full;
     ne->ws.n_cu = workspace(dev).n_cu;
     ne->n = n;
     hipError_t e = hipStreamCreateWithFlags(&ne->capture, hipStreamNonBlocking);

@@ -71,6 +71,9 @@ Workspace& workspace(int dev);
 
 struct PwlPieces;
 
+// Next value of the process-wide network version counter.
+uint64_t next_mlp_version();
+
 // The network handle behind sl7_mlp.
 struct Mlp {
   sl7_mlp_desc d;
@@ -87,7 +90,9 @@ struct Mlp {
   // compiled piecewise-linear forms by instance (model, dt, theta); cleared
   // with the device copies whenever the parameters change
   std::map<std::array<double, 5>, std::shared_ptr<PwlPieces>> pwl_cache;
-  uint64_t version = 0;  // bumped whenever the parameters change
+  // unique in the process: a fresh value on creation and whenever the
+  // parameters change, so (handle, version) never names two networks
+  uint64_t version = next_mlp_version();
 
   void layout();
   float W(int l, int o, int k) const;

@@ -66,6 +66,31 @@ def test_batched_graph_replays_match_eager(S, H):
         torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "pwl32"])
+def test_graph_replays_follow_the_networks_parameters(S, prec):
+    """A captured batch depends on the network's weights (the first-layer
+    constants go into its instance table, the piecewise-linear tables into
+    its workspace): after set_params, and for a new handle that replaces a
+    freed one, replays must give what an eager launch gives."""
+    prs = problems(S, 32, scale=0.1)
+    H1 = S.Mlp.load(CIR_WEIGHTS)
+    p0 = H1.params()
+    first = S.simulate_batched(prs, H1, prec=prec, seed=3, use_graph=True)
+    H1.set_params(p0 * np.float32(1.02))
+    got = S.simulate_batched(prs, H1, prec=prec, seed=3, use_graph=True)
+    ref = S.simulate_batched(prs, H1, prec=prec, seed=3, use_graph=False)
+    assert got == ref
+    assert got != first
+    del H1
+    for scale in (0.98, 1.0):
+        H2 = S.Mlp.load(CIR_WEIGHTS)
+        H2.set_params(p0 * np.float32(scale))
+        got = S.simulate_batched(prs, H2, prec=prec, seed=3, use_graph=True)
+        ref = S.simulate_batched(prs, H2, prec=prec, seed=3, use_graph=False)
+        assert got == ref, scale
+        del H2
+
+
 def test_batched_result_independent_of_instance_order(S, H):
     prs = problems(S, 32, scale=0.2)
     a = S.simulate_batched(prs, H, prec="bf16x3", seed=11, use_graph=False)
