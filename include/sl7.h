@@ -23,6 +23,10 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
  *     is enqueued on it; calls that return results into host memory
  *     synchronise that stream before returning, as documented per call.
+ *     Calls on one device share its internal buffers; the library orders
+ *     each call's work after the previous call's with an event, so calls
+ *     that do not synchronise may be issued from several threads on several
+ *     streams (their device work then runs one call after another).
  *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit
  *     seed, counter (step/4, path low word, path high word, tag) with
  *     tag = domain << 24 | instance, domain 0 for simulation and 1 for

@@ -155,8 +155,10 @@ extern "C" int sl7_adjoint(const sl7_problem* pr, const sl7_mlp* Hc, int prec, u
   rc = current_device(&dev);
   if (rc) return rc;
   Workspace& ws = workspace(dev);
-  std::lock_guard<std::mutex> lk(ws.mu);
   hipStream_t s = (hipStream_t)stream;
+  WsLease lease(ws, s);
+  rc = lease.begin();
+  if (rc) return rc;
   SimArgs sa;
   rc = prepare_instances(pr, 1, H, prec, seed, nullptr, s, ws, sa, /*pwl_theta=*/true);
   if (rc) return rc;

@@ -183,6 +183,22 @@ Workspace& workspace(int dev) {
   return *w;
 }
 
+int WsLease::begin() {
+  if (!ws_.done) {
+    const hipError_t e = hipEventCreateWithFlags(&ws_.done, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate(workspace)");
+  } else if (ws_.done_stream != s_) {
+    const hipError_t e = hipStreamWaitEvent(s_, ws_.done, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent(workspace)");
+  }
+  begun_ = true;
+  return SL7_OK;
+}
+
+WsLease::~WsLease() {
+  if (begun_ && hipEventRecord(ws_.done, s_) == hipSuccess) ws_.done_stream = s_;
+}
+
 int current_device(int* dev) {
   const hipError_t e = hipGetDevice(dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -856,8 +872,10 @@ int sl7_simulate(const sl7_problem* pr, const sl7_mlp* Hc, int prec, uint64_t se
   rc = current_device(&dev);
   if (rc) return rc;
   Workspace& ws = workspace(dev);
-  std::lock_guard<std::mutex> lk(ws.mu);
   hipStream_t s = (hipStream_t)stream;
+  WsLease lease(ws, s);
+  rc = lease.begin();
+  if (rc) return rc;
   rc = run_instances(pr, 1, H, prec, seed, YT_dev, plan, s, ws);
   if (rc) return rc;
   if (stats_host) return fetch_stats(ws, 1, stats_host, s);

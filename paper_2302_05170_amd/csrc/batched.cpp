@@ -99,7 +99,9 @@ extern "C" int sl7_simulate_batched(const sl7_problem* prs, int n, const sl7_mlp
   for (int k = 0; k < n; ++k) p[k].instance = prs[k].instance;
   if (!use_graph) {
     Workspace& ws = workspace(dev);
-    std::lock_guard<std::mutex> lk(ws.mu);
+    WsLease lease(ws, s);
+    rc = lease.begin();
+    if (rc) return rc;
     rc = run_instances(p.data(), n, H, prec, seed, nullptr, &plan, s, ws);
     if (rc) return rc;
     return fetch_stats(ws, n, stats_host, s);
@@ -303,7 +305,9 @@ extern "C" int sl7_autotune(const sl7_problem* shape, const sl7_mlp* Hc, int pre
   rc = current_device(&dev);
   if (rc) return rc;
   Workspace& ws = workspace(dev);
-  std::lock_guard<std::mutex> lk(ws.mu);
+  WsLease lease(ws, (hipStream_t)stream);
+  rc = lease.begin();
+  if (rc) return rc;
   // time on at least 2^20 paths so that each launch fills the chip for
   // several milliseconds
   sl7_problem sh = *shape;
@@ -339,7 +343,9 @@ extern "C" int sl7_autotune_batched(const sl7_problem* prs, int n, const sl7_mlp
   rc = current_device(&dev);
   if (rc) return rc;
   Workspace& ws = workspace(dev);
-  std::lock_guard<std::mutex> lk(ws.mu);
+  WsLease lease(ws, (hipStream_t)stream);
+  rc = lease.begin();
+  if (rc) return rc;
   std::vector<sl7_problem> p(prs, prs + n);
   sl7_plan best;
   float ms = 0.f;

@@ -65,9 +65,33 @@ struct Workspace {
   sl7_stats* stats_host = nullptr;
   int stats_host_n = 0;
   int stats_host_reserve(int n);
+  // end of the last call's work on the workspace, and the stream it ran on
+  hipEvent_t done = nullptr;
+  hipStream_t done_stream = nullptr;
 };
 
 Workspace& workspace(int dev);
+
+// One call's hold on a device workspace: its lock for the call, and its
+// buffers for the call's device work.  begin() makes the work enqueued on `s`
+// wait for the previous call's (which may be on another stream); the
+// destructor records the end of this call's work, so the next call waits for
+// it in turn.  Calls that do not synchronise may thus be issued on any
+// streams.
+class WsLease {
+ public:
+  WsLease(Workspace& ws, hipStream_t s) : ws_(ws), s_(s), lk_(ws.mu) {}
+  ~WsLease();
+  WsLease(const WsLease&) = delete;
+  WsLease& operator=(const WsLease&) = delete;
+  int begin();
+
+ private:
+  Workspace& ws_;
+  hipStream_t s_;
+  std::lock_guard<std::mutex> lk_;
+  bool begun_ = false;
+};
 
 struct PwlPieces;
 

@@ -205,6 +205,28 @@ def test_results_independent_of_launch_plan(S, H):
             assert st == outs[0][0]
 
 
+def test_asynchronous_calls_on_two_streams(S, H):
+    """Two calls that do not synchronise, on two streams, share the device's
+    workspace: the second call's uploads must wait for the first call's
+    kernels, and both results equal those of calls made one at a time."""
+    c = W.CONFIGS["gbm_mlp_2p22x16"]
+    pa = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
+    pb = S.Problem(c["model"], (0.25, 0.02), 1.1, 0.5, 4, c["m"], 70_001, K=1.0)
+    for prec in ("bf16x3", "pwl32", "f64"):
+        ref_a = gpu_yt(S, pa, H, prec, 1)[1]
+        ref_b = gpu_yt(S, pb, H, prec, 2)[1]
+        dt = torch.float64 if prec == "f64" else torch.float32
+        ya = torch.empty(pa.N, dtype=dt, device="cuda")
+        yb = torch.empty(pb.N, dtype=dt, device="cuda")
+        sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+        torch.cuda.synchronize()
+        S.simulate(pa, H, prec=prec, seed=1, yt=ya, stats=False, stream=sa)
+        S.simulate(pb, H, prec=prec, seed=2, yt=yb, stats=False, stream=sb)
+        torch.cuda.synchronize()
+        assert np.array_equal(ya.double().cpu().numpy(), ref_a), prec
+        assert np.array_equal(yb.double().cpu().numpy(), ref_b), prec
+
+
 def test_path_offset_shards_compose(S, H):
     c = W.CONFIGS["gbm_mlp_2p22x16"]
     full = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 6, c["m"], 3000, K=c["K"])
