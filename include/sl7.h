@@ -27,6 +27,11 @@
  *     each call's work after the previous call's with an event, so calls
  *     that do not synchronise may be issued from several threads on several
  *     streams (their device work then runs one call after another).
+ *   - A network handle may be read by several calls at once (simulation,
+ *     evaluation, adjoint).  Calls that change or free it (sl7_mlp_set_params,
+ *     sl7_train, sl7_mlp_free) must not overlap any other call that uses the
+ *     same handle; work already enqueued with it completes before its device
+ *     copies are released.
  *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit
  *     seed, counter (step/4, path low word, path high word, tag) with
  *     tag = domain << 24 | instance, domain 0 for simulation and 1 for

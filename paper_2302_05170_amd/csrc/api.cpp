@@ -267,6 +267,8 @@ uint64_t next_mlp_version() {
 }
 
 void Mlp::drop_device() {
+  // kernels already enqueued may still read these copies
+  if (device >= 0) (void)hipDeviceSynchronize();
   for (auto& p : pack) p.reset();
   net64.reset();
   lane64.reset();
@@ -805,7 +807,11 @@ int sl7_mlp_create(const sl7_mlp_desc* d, const float* params, sl7_mlp** out) {
   return SL7_OK;
 }
 
-void sl7_mlp_free(sl7_mlp* H) { delete reinterpret_cast<Mlp*>(H); }
+void sl7_mlp_free(sl7_mlp* H) {
+  Mlp* h = reinterpret_cast<Mlp*>(H);
+  if (h && h->device >= 0) (void)hipDeviceSynchronize();  // enqueued work may read its copies
+  delete h;
+}
 
 int sl7_mlp_get_desc(const sl7_mlp* H, sl7_mlp_desc* d) {
   if (!H || !d) return fail(SL7_EINVAL, "H and d must be non-NULL");

@@ -227,6 +227,26 @@ def test_asynchronous_calls_on_two_streams(S, H):
         assert np.array_equal(yb.double().cpu().numpy(), ref_b), prec
 
 
+def test_changing_a_network_waits_for_work_enqueued_with_it(S):
+    """set_params and free release the network's device copies; a launch
+    already enqueued with the old weights must still compute with them."""
+    c = W.CONFIGS["gbm_mlp_2p22x16"]
+    pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
+    for prec in ("bf16x3", "f64"):
+        H1 = S.Mlp.load(WEIGHTS)
+        p0 = H1.params()
+        ref = gpu_yt(S, pr, H1, prec, 5)[1]
+        y = torch.empty(pr.N, dtype=torch.float64 if prec == "f64" else torch.float32, device="cuda")
+        S.simulate(pr, H1, prec=prec, seed=5, yt=y, stats=False)
+        H1.set_params(p0 * np.float32(1.5))
+        torch.cuda.synchronize()
+        assert np.array_equal(y.double().cpu().numpy(), ref), prec
+        S.simulate(pr, H1, prec=prec, seed=5, yt=y, stats=False)
+        del H1
+        torch.cuda.synchronize()
+        assert not np.array_equal(y.double().cpu().numpy(), ref), prec
+
+
 def test_path_offset_shards_compose(S, H):
     c = W.CONFIGS["gbm_mlp_2p22x16"]
     full = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 6, c["m"], 3000, K=c["K"])
