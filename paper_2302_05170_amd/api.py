@@ -32,6 +32,18 @@ def _ptr(t) -> int | None:
     return t.data_ptr()
 
 
+def _check_tensor(name: str, t: torch.Tensor, dtype, shape) -> None:
+    """The library reads or writes `t` as a dense device array of `shape`:
+    refuse anything else here, where the tensor's size is still known."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype \
+            or tuple(t.shape) != tuple(int(v) for v in shape) or not t.is_contiguous():
+        got = (f"{tuple(t.shape)} {t.dtype} on {t.device}"
+               f"{'' if t.is_contiguous() else ', not contiguous'}"
+               if isinstance(t, torch.Tensor) else type(t).__name__)
+        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor of shape "
+                         f"{tuple(int(v) for v in shape)}; got {got}")
+
+
 def gh_nodes(m: int):
     """Probabilists' Gauss-Hermite nodes and weights (weights sum to 1)."""
     x = np.zeros(m)
@@ -150,9 +162,11 @@ def simulate(pr: Problem, H: Mlp | None = None, prec="f32", seed: int = 42, want
              stream=None):
     """Runs sl7_simulate.  Returns (stats dict or None, Y_T tensor or None)."""
     p = _prec(prec)
+    dt = torch.float64 if p in (L.F64, L.PWL64) else torch.float32
     if want_yt and yt is None:
-        dt = torch.float64 if p in (L.F64, L.PWL64) else torch.float32
         yt = torch.empty(int(pr.N), dtype=dt, device="cuda")
+    if yt is not None:
+        _check_tensor("yt", yt, dt, (int(pr.N),))
     st = L.Stats()
     pl = _plan(plan)
     cp = pr.c()
@@ -230,6 +244,7 @@ def eval_H(H: Mlp, inputs: torch.Tensor, prec="f32", out: torch.Tensor | None = 
     B = inputs.shape[0]
     if out is None:
         out = torch.empty((B, d.m), dtype=torch.float32, device=inputs.device)
+    _check_tensor("out", out, torch.float32, (B, d.m))
     L.check(L.lib().sl7_eval_H(H.handle, _prec(prec), _ptr(inputs), B, _ptr(out), _stream(stream)))
     return out
 
@@ -239,8 +254,10 @@ def labels(model: int, m: int, feats: torch.Tensor, n_paths: int = 10_000, subst
     """Euler-Maruyama quantile labels for feats [n, d_in] (CUDA float32)."""
     feats = feats.contiguous()
     n = feats.shape[0]
+    _check_tensor("feats", feats, torch.float32, (n, 2 + (2 if int(model) == L.GBM else 3)))
     if out is None:
         out = torch.empty((n, m), dtype=torch.float32, device=feats.device)
+    _check_tensor("out", out, torch.float32, (n, int(m)))
     L.check(L.lib().sl7_labels(int(model), int(m), _ptr(feats), n, int(n_paths), int(substeps),
                                int(seed), int(label0), _ptr(out), _stream(stream)))
     return out
@@ -253,12 +270,16 @@ def train(H: Mlp, X: torch.Tensor, Y: torch.Tensor, epochs: int, batch: int = 10
     X = X.contiguous()
     Y = Y.contiguous()
     n = X.shape[0]
+    d = H.desc()
+    _check_tensor("X", X, torch.float32, (n, d.d_in))
+    _check_tensor("Y", Y, torch.float32, (n, d.m))
     spec = L.TrainSpec()
     spec.epochs, spec.batch, spec.lr = int(epochs), int(batch), float(lr)
     spec.beta1, spec.beta2, spec.eps = float(betas[0]), float(betas[1]), float(eps)
     hist = np.zeros(int(epochs) * (n // int(batch)))
     if order is not None:
-        order = order.to(device=X.device, dtype=torch.int32).contiguous()
+        order = order.to(device=X.device, dtype=torch.int32).contiguous().reshape(-1)
+        _check_tensor("order", order, torch.int32, (int(epochs) * n,))
     L.check(L.lib().sl7_train(H.handle, ctypes.byref(spec), _ptr(X), _ptr(Y), n, _ptr(order),
                               hist.ctypes.data, _stream(stream)))
     return hist
@@ -268,6 +289,9 @@ def train_grad(H: Mlp, X: torch.Tensor, Y: torch.Tensor, stream=None):
     """Loss and its gradient over all rows of (X, Y): (loss, grad [n_params])."""
     X = X.contiguous()
     Y = Y.contiguous()
+    d = H.desc()
+    _check_tensor("X", X, torch.float32, (X.shape[0], d.d_in))
+    _check_tensor("Y", Y, torch.float32, (X.shape[0], d.m))
     g = torch.empty(H.n_params(), dtype=torch.float32, device=X.device)
     loss = ctypes.c_double()
     L.check(L.lib().sl7_train_grad(H.handle, _ptr(X), _ptr(Y), X.shape[0], _ptr(g),

@@ -226,3 +226,14 @@ def test_binding_fails_loudly_without_the_library(L, monkeypatch, tmp_path):
         S.Mlp.load(WEIGHTS)
     with pytest.raises(RuntimeError, match="is missing"):
         S.gh_nodes(5)
+
+
+def test_binding_refuses_tensors_it_cannot_size(L):
+    """The C ABI takes bare device pointers; the binding checks every caller
+    tensor against the shape the library will read or write before the call
+    (here a host tensor, refused without touching a device)."""
+    import torch
+    import paper_2302_05170_amd as S
+    pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 4, 5, 100)
+    with pytest.raises(ValueError, match="yt must be"):
+        S.simulate(pr, None, prec="f32", yt=torch.empty(100))

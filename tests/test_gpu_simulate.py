@@ -247,6 +247,19 @@ def test_changing_a_network_waits_for_work_enqueued_with_it(S):
         assert not np.array_equal(y.double().cpu().numpy(), ref), prec
 
 
+def test_binding_refuses_mismatched_output_tensors(S, H):
+    """Short, mistyped or strided output tensors are refused by the binding
+    before the library could write past them."""
+    pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 4, 5, 1000)
+    for bad in (torch.empty(999, device="cuda"), torch.empty(1000, dtype=torch.float64, device="cuda"),
+                torch.empty(2000, device="cuda")[::2]):
+        with pytest.raises(ValueError, match="yt must be"):
+            S.simulate(pr, H, prec="f32", yt=bad)
+    x = torch.zeros((10, 4), device="cuda")
+    with pytest.raises(ValueError, match="out must be"):
+        S.eval_H(H, x, prec="f32", out=torch.empty((10, 4), device="cuda"))
+
+
 def test_path_offset_shards_compose(S, H):
     c = W.CONFIGS["gbm_mlp_2p22x16"]
     full = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 6, c["m"], 3000, K=c["K"])
