@@ -248,11 +248,11 @@ def test_piecewise_linear_adjoint_on_cir(S):
 
 
 @pytest.mark.parametrize("m2", [3, 8])
-def test_adjoint_other_node_counts(S, H, m2, tmp_path):
+def test_adjoint_other_node_counts(S, m2, tmp_path):
     """Networks with 3 and 8 outputs (the stored head re-interpolated onto
     the other node sets): network and piecewise-linear reverse sweeps against
     the oracle's per-path tangents, FP64."""
-    H2, Ho2 = network_with_m_outputs(S, H, m2, str(tmp_path / f"gbm_m{m2}.sl7w"))
+    H2, Ho2 = network_with_m_outputs(S, m2, str(tmp_path / f"gbm_m{m2}.sl7w"))
     pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 9, m2, 1500, K=1.0)
     f, df = oracle_pathwise(pr, Ho2, 23, 1, pr.N)
     for prec in ("f64", "pwl64"):

@@ -339,10 +339,10 @@ def test_eval_H_f64_second_grid_row(S, H, Ho):
 
 
 @pytest.mark.parametrize("m2", [2, 3, 4, 6, 8])
-def test_every_node_count_in_every_network_mode(S, H, m2, tmp_path):
+def test_every_node_count_in_every_network_mode(S, m2, tmp_path):
     """Each kernel is specialised on m: networks with 2..8 outputs (other than
     the stored 5 and 7) against the oracle in every network mode."""
-    H2, Ho2 = network_with_m_outputs(S, H, m2, str(tmp_path / f"gbm_m{m2}.sl7w"))
+    H2, Ho2 = network_with_m_outputs(S, m2, str(tmp_path / f"gbm_m{m2}.sl7w"))
     c = W.CONFIGS["gbm_mlp_2p22x16"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 7, m2, 1000, K=c["K"])
     ref = orc(pr, Ho2, 17, np.arange(pr.N))
