@@ -208,13 +208,16 @@ def test_gpu_offline_stage_for_the_papers_ou_network(S):
     order = W.minibatch_order(n_lab, epochs, seed=W.TRAIN_SEED)
     hist = S.train(H, Xd, Yd, epochs=epochs, batch=W.BATCH,
                    order=torch.tensor(order.ravel(), dtype=torch.int32))
-    Ht = H0.with_params(H.params())
-    f = W.ou_features(2000, seed=123)
+    # the trained network evaluated by the library's FP64 mode (eval_H, held
+    # to the oracle's forward pass by its own parity test)
+    f = W.ou_features(2000, seed=123).astype(np.float32).astype(np.float64)
     x, _ = oracle.gh_nodes(5)
     Y, dt, ybar, sig, lam = f.T
     e = np.exp(-lam * dt)
     exact = (Y * e + ybar * (1 - e))[:, None] + (sig * np.sqrt((1 - e * e) / (2 * lam)))[:, None] * x
-    err = Ht.forward(f) - exact
+    out = S.eval_H(H, cuda32(f), prec="f64")
+    torch.cuda.synchronize()
+    err = out.double().cpu().numpy() - exact
     rms = float(np.sqrt(np.mean(err ** 2)))
     print(f"GPU-trained OU network: loss {hist[0]:.3e} -> {hist[-32:].mean():.3e}; "
           f"vs closed form rms {rms:.2e}, max {np.abs(err).max():.2e}")
