@@ -46,7 +46,7 @@ def problems(S, n=256, scale=1.0):
     return out
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["bf16x3", "f32", "bf16", "f16x3", "f16", "pwl32", "pwl64"])
 def test_batched_equals_single_instance_runs(S, H, prec):
     prs = problems(S, 40, scale=0.25)
     got = S.simulate_batched(prs, H, prec=prec, seed=11, use_graph=False)
