@@ -274,3 +274,16 @@ def test_adjoint_second_grid_row(S):
     f, df = oracle.simulate_tangent(opr, None, 31, idx)
     assert np.max(np.abs(pp[:, 0] - f)) <= 1e-12 * (1 + np.max(np.abs(f)))
     assert np.max(np.abs(pp[:, 1:] - df) / (1 + np.abs(df))) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["f64", "pwl64"])
+def test_adjoint_path_indices_beyond_32_bits(S, H, Ho, prec):
+    """A shard straddling global path index 2^32 (both Philox path words):
+    per-path sensitivities against the oracle's tangents at the same global
+    indices, network and piecewise-linear sweeps."""
+    off, N = 2 ** 32 - 500, 1000
+    pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 6, 5, N, K=1.0, path_offset=off)
+    g, pp = S.adjoint(pr, H, prec=prec, seed=19, payoff=0, ckpt_every=4, per_path=True)
+    opr = oracle.Problem(pr.model, pr.theta, pr.Y0, pr.T, pr.M, pr.m, pr.instance)
+    f, df = oracle.simulate_tangent(opr, Ho, 19, off + np.arange(N, dtype=np.int64))
+    check_pathwise(pp.cpu().numpy(), f, df, g)
