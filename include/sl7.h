@@ -216,9 +216,11 @@ int sl7_pwl_compile(const sl7_mlp* H, const sl7_problem* pr, int max_pieces, int
 /* Many instances of uneven size in one persistent launch (network map,
  * every prec but F64; all instances share m).  Work is 64-path blocks
  * ordered longest-M first and handed out by an atomic work counter; per-instance statistics go to
- * stats_host[n] (synchronises the stream).  The launch sequence is captured
- * once into a hipGraph per distinct (prec, instance table) signature and
- * replayed when use_graph != 0. */
+ * stats_host[n] (synchronises the stream).  With use_graph != 0 the launch
+ * sequence is captured once into a hipGraph, with buffers of its own, and
+ * replayed by later calls whose problems, plan, seed, prec, device and
+ * network weights are all the same (a change of H's parameters makes a new
+ * capture); at most 8 captures are kept. */
 int sl7_simulate_batched(const sl7_problem* prs, int n, const sl7_mlp* H,
                          int prec, uint64_t seed, sl7_stats* stats_host,
                          const sl7_plan* plan, int use_graph, void* stream);
