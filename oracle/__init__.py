@@ -110,6 +110,11 @@ def _declare(L):
     L.orc_mlp_forward.argtypes = [_P, _P, _P]
     L.orc_simulate.argtypes = [_P, _P, _P, _P, ctypes.c_uint64, _P, ctypes.c_int64, _P, _P]
     L.orc_simulate_tangent.argtypes = [_P, _P, _P, _P, ctypes.c_uint64, _P, ctypes.c_int64, _P, _P]
+    L.orc_cdc_tables.argtypes = [_P, _P, _P, _P, _P, _P, _P]
+    L.orc_cdc_tables.restype = ctypes.c_int
+    L.orc_cdc_collocation.argtypes = [ctypes.c_int, ctypes.c_int, _P, _P, _P, ctypes.c_double, _P]
+    L.orc_simulate_cdc.argtypes = [_P, _P, _P, _P, _P, _P, ctypes.c_uint64, _P, ctypes.c_int64,
+                                   _P, _P]
     L.orc_em_paths.argtypes = [ctypes.c_int, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                ctypes.c_uint64, ctypes.c_uint32, _P, ctypes.c_int64, _P]
     L.orc_em_label.argtypes = [ctypes.c_int, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
@@ -427,6 +432,61 @@ def simulate_tangent(pr: Problem, H: Mlp | None, seed: int, paths, threads: int 
     with ThreadPoolExecutor(threads or n_threads()) as ex:
         list(ex.map(run, _chunks(paths, threads or n_threads())))
     return YT, dYT
+
+
+def cdc_tables(pr: Problem, H: Mlp | None):
+    """Per-step tables of the 7L-CDC variant: marginal points s [M, m], their
+    barycentric weights [M, m] and the conditional points at them ykj
+    [M, m, m] (row 0: the conditional points at Y0 in k = 0).  Also returns
+    the count of network inputs outside the training domain."""
+    x, _ = gh_nodes(pr.m)
+    ps = _problem_struct(pr, H)
+    hs, keep = (H._struct() if H is not None else (None, None))
+    s = np.zeros((pr.M, pr.m))
+    lams = np.zeros((pr.M, pr.m))
+    ykj = np.zeros((pr.M, pr.m, pr.m))
+    cnt = np.zeros(2, dtype=np.int64)
+    rc = lib().orc_cdc_tables(ctypes.byref(ps), ctypes.byref(hs) if hs is not None else None,
+                              _ptr(x), _ptr(s), _ptr(lams), _ptr(ykj), _ptr(cnt))
+    if rc != 0:
+        raise ValueError(f"7L-CDC: marginal collocation points of step {-1 - rc} are not distinct")
+    return s, lams, ykj, int(cnt[1])
+
+
+def cdc_collocation(tables, i: int, Y: float) -> np.ndarray:
+    """Conditional collocation points of a path at Y in step i (the global
+    interpolation)."""
+    s, lams, ykj = (np.ascontiguousarray(t, np.float64) for t in tables[:3])
+    m = s.shape[1]
+    out = np.zeros(m)
+    lib().orc_cdc_collocation(m, i, _ptr(s), _ptr(lams), _ptr(ykj), float(Y), _ptr(out))
+    return out
+
+
+def simulate_cdc(pr: Problem, H: Mlp | None, seed: int, paths, threads: int | None = None):
+    """Y_T of the listed global paths under the 7L-CDC variant.  Returns
+    (YT, n_clamped, n_out_of_domain of the table evaluations)."""
+    paths = np.ascontiguousarray(paths, dtype=np.int64)
+    x, _ = gh_nodes(pr.m)
+    lam = bary_weights(x)
+    s, lams, ykj, nood = cdc_tables(pr, H)
+    ps = _problem_struct(pr, H)
+    YT = np.empty(len(paths))
+    counts = []
+
+    def run(rng):
+        a, b = rng
+        cnt = np.zeros(2, dtype=np.int64)
+        lib().orc_simulate_cdc(ctypes.byref(ps), _ptr(x), _ptr(lam), _ptr(s), _ptr(lams),
+                               _ptr(ykj), seed, _ptr(paths[a:b]), b - a, _ptr(YT[a:b]),
+                               _ptr(cnt))
+        return cnt
+
+    with ThreadPoolExecutor(threads or n_threads()) as ex:
+        for cnt in ex.map(run, _chunks(paths, threads or n_threads())):
+            counts.append(cnt)
+    tot = np.sum(counts, axis=0) if counts else np.zeros(2, np.int64)
+    return YT, int(tot[0]), nood
 
 
 def em_paths(pr: Problem, seed: int, paths) -> np.ndarray:

@@ -388,6 +388,111 @@ void orc_simulate_tangent(const orc_problem* pr, const orc_mlp* H,
   }
 }
 
+/* ------------------------------------------------------------------------ */
+/* The 7L-CDC variant (Numerical Results, the paragraph after Table 6.1; the  */
+/* paper defers its definition to its ref. [1] and describes it in outline:   */
+/* the network gives a few marginal collocation points, a global             */
+/* interpolation over them replaces the per-path network call, and each step */
+/* takes two interpolations).  Reading used here:                            */
+/*   - marginal points of step i >= 1: s_k = (map over [0, t_i] from Y0)_k,  */
+/*     the collocation points of the law of Y(t_i) given Y(0) = Y0;           */
+/*   - conditional points computed only there: y_kj = (map over dt at s_k)_j */
+/*     (m map evaluations per step instead of one per path);                 */
+/*   - a path at Y_i takes y_j(Y_i) = sum_k l_k(Y_i) y_kj, l_k the Lagrange   */
+/*     basis over the nodes s_0..s_{m-1} in Y (barycentric, second form, the */
+/*     same routine as the step's interpolation), then Y_{i+1} = g_m(X);      */
+/*   - step 0: the law of Y(0) is the point mass at Y0, so y_j = map(Y0)_j.   */
+/* The map is the network (H != NULL) or the analytic map.                   */
+/* ------------------------------------------------------------------------ */
+
+/* The collocation map over a step of length h from state Y (network or
+ * analytic); counts[1] += 1 when a network input Y lies outside its domain. */
+static void orc_map(const orc_problem* pr, const orc_mlp* H, const double* x,
+                    double Y, double h, double* y, int64_t* counts) {
+  if (H) {
+    double in[16];
+    orc_mlp_input(pr, Y, h, in);
+    if (counts && (Y < pr->dom_lo || Y > pr->dom_hi)) counts[1] += 1;
+    orc_mlp_forward(H, in, y);
+  } else {
+    orc_analytic_map(pr->model, pr->theta, Y, h, pr->m, x, y);
+  }
+}
+
+/* Per-step tables of the CDC variant: s[i*m + k] marginal points,
+ * lams[i*m + k] their barycentric weights 1 / prod_{l != k} (s_k - s_l),
+ * ykj[(i*m + k)*m + j] conditional points at s_k.  Row i = 0 holds Y0 and
+ * the conditional points at Y0 in k = 0 (s and lams unused).  Returns 0, or
+ * -1 - i when the marginal points of step i are not distinct. */
+int orc_cdc_tables(const orc_problem* pr, const orc_mlp* H, const double* x,
+                   double* s, double* lams, double* ykj, int64_t* counts) {
+  const int m = pr->m, M = pr->M;
+  const double dt = pr->T / M;
+  for (int i = 0; i < M; ++i) {
+    double* si = s + (int64_t)i * m;
+    double* li = lams + (int64_t)i * m;
+    double* yi = ykj + (int64_t)i * m * m;
+    if (i == 0) {
+      for (int k = 0; k < m; ++k) { si[k] = pr->Y0; li[k] = 0.0; }
+      for (int k = 0; k < m * m; ++k) yi[k] = 0.0;
+      orc_map(pr, H, x, pr->Y0, dt, yi, counts);
+      continue;
+    }
+    const double ti = i * pr->T / M;
+    orc_map(pr, H, x, pr->Y0, ti, si, counts);
+    for (int k = 0; k < m; ++k) {
+      double prod = 1.0;
+      for (int l = 0; l < m; ++l) {
+        if (l == k) continue;
+        if (si[k] == si[l]) return -1 - i;
+        prod *= si[k] - si[l];
+      }
+      li[k] = 1.0 / prod;
+    }
+    for (int k = 0; k < m; ++k) orc_map(pr, H, x, si[k], dt, yi + k * m, counts);
+  }
+  return 0;
+}
+
+/* Conditional collocation points of a path at Y in step i (the global
+ * interpolation, one barycentric evaluation per output j). */
+void orc_cdc_collocation(int m, int i, const double* s, const double* lams,
+                         const double* ykj, double Y, double* y) {
+  const double* yi = ykj + (int64_t)i * m * m;
+  if (i == 0) {
+    for (int j = 0; j < m; ++j) y[j] = yi[j];
+    return;
+  }
+  double col[16];
+  for (int j = 0; j < m; ++j) {
+    for (int k = 0; k < m; ++k) col[k] = yi[k * m + j];
+    y[j] = orc_bary(m, s + (int64_t)i * m, lams + (int64_t)i * m, col, Y);
+  }
+}
+
+/* Simulates the listed global paths with the CDC variant (same normals and
+ * clamp as orc_simulate); counts[0] += CIR clamp events. */
+void orc_simulate_cdc(const orc_problem* pr, const double* x, const double* lam,
+                      const double* s, const double* lams, const double* ykj,
+                      uint64_t seed, const int64_t* paths, int64_t count,
+                      double* YT, int64_t* counts) {
+  double y[16];
+  for (int64_t c = 0; c < count; ++c) {
+    int64_t p = paths[c];
+    double Y = pr->Y0;
+    for (int i = 0; i < pr->M; ++i) {
+      orc_cdc_collocation(pr->m, i, s, lams, ykj, Y, y);
+      double X = orc_step_normal(seed, pr->tag, p, i);
+      Y = orc_bary(pr->m, x, lam, y, X);
+      if (pr->model == ORC_CIR && Y < 0.0) {
+        Y = 0.0;
+        counts[0] += 1;
+      }
+    }
+    YT[c] = Y;
+  }
+}
+
 /* Large-step Euler-Maruyama (eq. 6.2) driven by the same normals as the 7L
  * paths: the scheme "without the network" at the same M. */
 void orc_em_paths(int model, const double* theta, double Y0, double T, int M,
