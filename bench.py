@@ -117,21 +117,58 @@ def sampled_error(S, pr, H, prec, seed, sub, ref):
     return float(r.max()), float(np.quantile(r, 0.99)), len(sub)
 
 
-def cpu_baseline(pr, seed, n_paths):
-    """The oracle (FP64, plain C, all host cores) on a bounded sample."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pr, seed, n_paths, n_paths_1t):
+    """The oracle (FP64, plain C) on a bounded sample of the workload's paths:
+    the median of three runs on all host threads, and one single-thread run
+    on a smaller prefix."""
     import oracle
     Ho = oracle.load_mlp(WEIGHTS)
     threads = oracle.n_threads()
     paths = np.arange(n_paths)
     opr = oracle.Problem(pr.model, pr.theta, pr.Y0, pr.T, pr.M, pr.m)
     oracle.simulate(opr, Ho, seed, paths[:256], threads=threads)
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.simulate(opr, Ho, seed, paths, threads=threads)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
     t0 = time.perf_counter()
-    oracle.simulate(opr, Ho, seed, paths, threads=threads)
-    dt = time.perf_counter() - t0
+    oracle.simulate(opr, Ho, seed, paths[:n_paths_1t], threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": n_paths * pr.M / dt, "unit": "path-steps/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"first {n_paths} of the {pr.N} paths x {pr.M} steps, FP64 network map, "
-                      f"{dt:.1f} s wall on {threads} threads"}
+            "sample": f"first {n_paths} of the {pr.N} paths x {pr.M} steps, FP64 network map; "
+                      f"median of 3 runs ({', '.join(f'{t:.2f}' for t in times)} s) on "
+                      f"{threads} threads",
+            "cpu_model": cpu_model(), "host_nproc": os.cpu_count(),
+            "single_thread": {"value": n_paths_1t * pr.M / dt1, "unit": "path-steps/s",
+                              "sample": f"first {n_paths_1t} paths, {dt1:.2f} s on 1 thread"}}
+
+
+def weak_errors(res, st1, c2, c1):
+    """E[Y_T] of each mode against the closed form Y0 exp(mu T) of GBM, beside
+    Euler-Maruyama with the same M large steps, whose mean Y0 (1 + mu dt)^M is
+    exact for GBM."""
+    out = {}
+    for name, cfg, stats in (("gbm_2p24x32", c2, {p: r["st"] for p, r in res.items()}),
+                             ("gbm_2p22x16", c1, {"f32": st1})):
+        mu, T, M, Y0 = cfg["theta"][1], cfg["T"], cfg["M"], cfg["Y0"]
+        exact = Y0 * math.exp(mu * T)
+        row = {p: {"weak_error": s["mean"][0] - exact, "se": s["se"][0]} for p, s in stats.items()}
+        row["euler_same_steps"] = Y0 * (1.0 + mu * T / M) ** M - exact
+        out[name] = row
+    return out
 
 
 def main():
@@ -140,7 +177,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-paths", type=int, default=2 ** 21)
+    ap.add_argument("--cpu-paths", type=int, default=2 ** 19)
+    ap.add_argument("--cpu-paths-1t", type=int, default=2 ** 15)
     ap.add_argument("--profile-run", default=None,
                     help="only run the default workload in this precision (plus a 256 MiB "
                          "calibration copy) for rocprofv3; prints no JSON.  adjoint_f64 / "
@@ -231,6 +269,9 @@ def main():
                      K=d["theta"][1], instance=d["instance"]) for d in W.cir_instances(256)]
     ps4 = sum(p.N * p.M for p in prs)
     batched = {}
+    # per-instance means of the library's FP64 mode (single-instance runs), the
+    # reference for each batched mode's error
+    ref4 = np.array([S.simulate(p, Hc, prec="f64", seed=11)[0]["mean"] for p in prs])
     # the batch tuner times every candidate plan on the 256 instances themselves
     # (not run for the FP32 comparator: 55 candidates of 60 ms launches)
     for prec in ("bf16x3", "bf16", "f32", "pwl32"):
@@ -239,7 +280,12 @@ def main():
         for name, plan in (("default", None), ("tuned", tuned)):
             if name == "tuned" and tuned is None:
                 continue
-            S.simulate_batched(prs, Hc, prec=prec, seed=11, plan=plan, use_graph=True)
+            got4 = np.array([s["mean"] for s in S.simulate_batched(prs, Hc, prec=prec, seed=11,
+                                                                   plan=plan, use_graph=True)])
+            if name == "default":
+                e4 = np.abs(got4 - ref4) / np.abs(ref4)
+                row["max_rel_err_of_instance_means_vs_fp64"] = {"Y_T": float(e4[:, 0].max()),
+                                                                "call": float(e4[:, 1].max())}
             reps = 5 if prec != "f32" else 2
             t0 = time.perf_counter()
             for _ in range(reps):
@@ -247,7 +293,8 @@ def main():
             dt = (time.perf_counter() - t0) / reps
             row[name] = {"path_steps_per_s": ps4 / dt, "ms_per_launch": dt * 1e3}
             log(f"batched {prec} ({name} plan {plan}): {ps4 / dt:.3e} path-steps/s "
-                f"({dt * 1e3:.2f} ms per replay)")
+                f"({dt * 1e3:.2f} ms per replay); instance means vs FP64: "
+                f"{row['max_rel_err_of_instance_means_vs_fp64']}")
         batched[prec] = row
 
     # the network in its exact piecewise-linear form along Y (ReLU networks):
@@ -282,6 +329,17 @@ def main():
                     "mean_YT": st_o["mean"][0], "paper_mx150_s": PAPER_T61_PARALLEL_S[n]}
             log(f"OU 4x50 softplus {prec}: " + ", ".join(
                 f"N={k} {v['ms_per_run']:.3f} ms" for k, v in ou[prec].items()))
+        # per-path error at the largest path count against the library's FP64
+        # mode (floor 0.5, the path scale: OU paths cross zero)
+        n = max(P["path_counts"])
+        pro = S.Problem(P["model"], P["theta"], P["Y0"], P["T"], P["M"], P["m"], n, K=P["K"])
+        _, y64 = S.simulate(pro, Hou, prec="f64", seed=P["seed"], want_yt=True, stats=False)
+        y64 = y64.cpu().numpy()
+        for prec in ("bf16x3", "f32"):
+            _, yp = S.simulate(pro, Hou, prec=prec, seed=P["seed"], want_yt=True, stats=False)
+            e = np.abs(yp.double().cpu().numpy() - y64) / np.maximum(np.abs(y64), 0.5)
+            ou[prec]["max_rel_err_vs_fp64_2e5_paths"] = float(e.max())
+            log(f"OU 4x50 softplus {prec}: max per-path error {e.max():.2e} at N={n}")
         # pathwise Greeks of E[max(Y_T - K, 0)] w.r.t. (Y0, ybar, sigma, lambda) through
         # the Softplus network, at the largest path count
         n = max(P["path_counts"])
@@ -346,7 +404,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": "bf16x3",
         "data": "synthetic (Philox normals; network trained by the project on synthetic EM labels)",
         "config": {"workload": "GBM network map, N=2^24 paths, M=32 steps, sigma=0.4, mu=0.05, "
                                "T=2, m=5, MLP 4-64x4-5 ReLU", "N": c["N"], "M": c["M"],
@@ -362,6 +420,7 @@ def main():
                 "max_rel_err_vs_fp64": r["emax"], "p99_rel_err": r["e99"],
                 "sampled_paths": r["ns"], "mean_YT": r["st"]["mean"][0], "se_YT": r["st"]["se"][0]}
             for p, r in res.items()},
+        "weak_error_vs_closed_form": weak_errors(res, st1, c, g16),
         "bf16x3_minus_f32_mean_over_se": (b["st"]["mean"][0] - res["f32"]["st"]["mean"][0]) / se_pair,
         "speedup_vs_f32_mfma": res["f32"]["wall"] / b["wall"],
         "gbm_2p22x16_f32_path_steps_per_s": g16["N"] * g16["M"] / wall1,
@@ -376,7 +435,7 @@ def main():
                     "ou_softplus_4x50": off_ou},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pr, c["seed"], args.cpu_paths)
+        out["cpu_baseline"] = cpu_baseline(pr, c["seed"], args.cpu_paths, args.cpu_paths_1t)
         log(f"cpu baseline: {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 

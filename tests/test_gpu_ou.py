@@ -5,15 +5,19 @@ Softplus units, Numerical Results section), at the path counts of Table 6.1.
 The 50-unit layers run zero-padded to 64 on the MFMA kernels.  OU paths cross
 zero, so the per-path error is taken against max(|oracle|, 0.5), the path
 scale (the same reading as the analytic OU test).  Tolerances as for GBM
-(FP64 1e-12, split BF16 2e-3, split FP16 5e-4, the one-pass modes against
-sanity bounds, 0.5 / 0.1, twice the worst error measured on this network:
-the weights rounded once make a fixed bias in every step, which the tail
-paths below amplify) except FP32, 2e-5: the worst paths are those whose
-normal lies beyond the outer nodes (|X| > 4.5 at 2e5 paths), where the
-degree-4 interpolant extrapolates and multiplies the network's FP32 output
-rounding (rms 2e-7 here) by the Lebesgue function (43 at |X| = 4.5, 89 at
-5.2).  A correctly rounded FP32 evaluation of the same paths in numpy
-already reaches 7e-6.
+(FP64 1e-12, FP32 1e-5, split BF16 2e-3, split FP16 5e-4, the one-pass modes
+against sanity bounds, 0.5 / 0.1, twice the worst error measured on this
+network: the weights rounded once make a fixed bias in every step, which the
+tail paths below amplify).
+
+FP32: the 1e-5 bound holds for every path whose normals stay inside
+|X| <= 4 at all steps.  A path that draws |X| > 4 extrapolates the degree-4
+interpolant there, which multiplies the network's FP32 output error (rms
+2.2e-7 measured on this network) by the Lebesgue function (22 at |X| = 4,
+43 at 4.5, 89 at 5.2); those paths (about 1 in 2000) are held to 2e-5.  A
+plain FP32 evaluation of this network and interpolant on the CPU, with
+rounded products and sequential FP32 sums, reaches the same size of error
+on the same paths.
 """
 import os
 
@@ -28,8 +32,10 @@ pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 WEIGHTS = os.path.join(ROOT, "tests", "golden", "ou_mlp_5x50_softplus.sl7w")
-TOL = {"f64": 1e-12, "f32": 2e-5, "bf16x3": 2e-3, "f16x3": 5e-4, "bf16": 0.5, "f16": 0.1}
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16x3": 2e-3, "f16x3": 5e-4, "bf16": 0.5, "f16": 0.1}
 PAPER = W.OU_PAPER
+# FP32 bound for paths that draw a normal with |X| > 4 (extrapolation)
+F32_EXTRAPOLATING = 2e-5
 
 
 @pytest.fixture(scope="module")
@@ -66,13 +72,15 @@ def gpu_yt(S, pr, H, prec, seed):
 
 @pytest.fixture(scope="module")
 def ref_paths(S, Ho):
-    """Oracle Y_T for every path at the largest path count of Table 6.1; the
-    smaller counts are prefixes of it (same seed, global path indices)."""
+    """Oracle Y_T for every path at the largest path count of Table 6.1 (the
+    smaller counts are prefixes of it: same seed, global path indices) and
+    each path's largest |X| over the steps."""
     N = max(PAPER["path_counts"])
     pr = problem(S, N)
     opr = oracle.Problem(pr.model, pr.theta, pr.Y0, pr.T, pr.M, pr.m, pr.instance)
     y, _, _ = oracle.simulate(opr, Ho, PAPER["seed"], np.arange(N))
-    return y
+    X = oracle.step_normals(PAPER["seed"], oracle.make_tag(0, pr.instance), np.arange(N), pr.M)
+    return y, np.abs(X).max(axis=1)
 
 
 def test_network_is_the_papers_shape(H, Ho):
@@ -84,14 +92,20 @@ def test_network_is_the_papers_shape(H, Ho):
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "f16x3", "bf16", "f16"])
 def test_table61_path_counts(S, H, ref_paths, prec):
+    ref_all, xmax_all = ref_paths
     for N in PAPER["path_counts"]:
         st, y = gpu_yt(S, problem(S, N), H, prec, PAPER["seed"])
-        e = err(y, ref_paths[:N])
-        print(f"OU softplus {prec} N={N} max err {e.max():.3e}")
+        e = err(y, ref_all[:N])
+        inner = xmax_all[:N] <= 4.0
+        print(f"OU softplus {prec} N={N} max err {e.max():.3e}; paths with all |X| <= 4: "
+              f"{e[inner].max():.3e}; {np.count_nonzero(~inner)} extrapolating paths: "
+              f"{e[~inner].max() if np.any(~inner) else 0.0:.3e}")
         assert st["n"] == N
-        assert e.max() <= TOL[prec], (prec, N, e.max())
+        assert e[inner].max() <= TOL[prec], (prec, N, e[inner].max())
+        bound = F32_EXTRAPOLATING if prec == "f32" else TOL[prec]
+        assert e.max() <= bound, (prec, N, e.max())
         if prec in ("f64", "f32"):
-            f = oracle.estimate(ref_paths[:N])
+            f = oracle.estimate(ref_all[:N])
             assert abs(st["mean"][0] - f["mean"]) <= (1e-12 if prec == "f64" else 1e-6) * max(
                 abs(f["mean"]), 0.5)
 

@@ -144,19 +144,24 @@ def test_mlp_f32_paths_and_means(S, H, Ho):
         assert abs(st["mean"][k] - e["mean"]) <= 1e-6 * abs(e["mean"]), k
 
 
-def test_gbm_2p22x16_full_size_sampled_paths(S, H, Ho):
-    """N = 2^22, M = 16, the benchmark's default plan; the oracle recomputes
-    the first and last 2^15 paths and a strided 2^16."""
+def test_gbm_2p22x16_full_size_every_path_and_means(S, H, Ho):
+    """The full 2^22 x 16 workload in FP32 with the benchmark's default plan:
+    the oracle recomputes every path, so each Y_T is checked at 1e-5 and
+    both payoff means at 1e-6 relative."""
     c = W.CONFIGS["gbm_mlp_2p22x16"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
     st, y = gpu_yt(S, pr, H, "f32", c["seed"])
-    sub = W.parity_subset(c["N"])
-    ref = orc(pr, Ho, c["seed"], sub)
-    r = rel(y[sub], ref)
-    print(f"f32 GBM 2^22 x 16 full: max rel {r.max():.3e} over {len(sub)} paths")
+    ref = orc(pr, Ho, c["seed"], np.arange(c["N"]))
+    r = rel(y, ref)
+    print(f"f32 GBM 2^22 x 16 full: max rel {r.max():.3e} p99 {np.quantile(r, 0.99):.3e} "
+          f"over {c['N']} paths")
     assert r.max() <= TOL["f32"]
     assert st["n"] == c["N"]
-    assert abs(st["mean"][0] - y.mean()) <= 1e-9 * abs(y.mean())
+    for k, f in enumerate(oracle.payoffs(ref, c["K"])):
+        e = oracle.estimate(f)
+        d = abs(st["mean"][k] - e["mean"]) / abs(e["mean"])
+        print(f"  payoff {k}: mean {st['mean'][k]:.9f} oracle {e['mean']:.9f} rel {d:.2e}")
+        assert d <= 1e-6, k
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "f16x3", "f32", "bf16", "f16"])
