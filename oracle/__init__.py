@@ -103,6 +103,8 @@ def _declare(L):
     L.orc_normals4.argtypes = [ctypes.c_uint64] + [ctypes.c_uint32] * 4 + [_P]
     L.orc_step_normal.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int]
     L.orc_step_normal.restype = ctypes.c_double
+    L.orc_step_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint32, _P, ctypes.c_int64,
+                                   ctypes.c_int, _P]
     L.orc_Phi.argtypes = [ctypes.c_double]
     L.orc_Phi.restype = ctypes.c_double
     L.orc_bary.argtypes = [ctypes.c_int, _P, _P, _P, ctypes.c_double]
@@ -211,14 +213,18 @@ def make_tag(domain: int, instance: int) -> int:
     return ((domain & 0xFF) << 24) | (instance & 0xFFFFFF)
 
 
-def step_normals(seed: int, tag: int, paths, M: int) -> np.ndarray:
+def step_normals(seed: int, tag: int, paths, M: int, threads: int | None = None) -> np.ndarray:
     """X[c, i]: the normal driving large step i of global path paths[c]."""
-    L = lib()
-    paths = np.asarray(paths, dtype=np.int64)
+    paths = np.ascontiguousarray(paths, dtype=np.int64)
     out = np.empty((len(paths), M))
-    for c, p in enumerate(paths):
-        for i in range(M):
-            out[c, i] = L.orc_step_normal(seed, tag, int(p), i)
+
+    def run(rng):
+        a, b = rng
+        lib().orc_step_normals(seed, tag, _ptr(paths[a:b]), b - a, M, _ptr(out[a:b]))
+
+    nt = threads or n_threads()
+    with ThreadPoolExecutor(nt) as ex:
+        list(ex.map(run, _chunks(paths, nt)))
     return out
 
 

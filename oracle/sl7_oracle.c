@@ -85,6 +85,13 @@ double orc_step_normal(uint64_t seed, uint32_t tag, int64_t path, int step) {
   return n4[step % 4];
 }
 
+/* The normals of steps 0..M-1 of each listed path, out[c*M + i]. */
+void orc_step_normals(uint64_t seed, uint32_t tag, const int64_t* paths, int64_t count, int M,
+                      double* out) {
+  for (int64_t c = 0; c < count; ++c)
+    for (int i = 0; i < M; ++i) out[c * M + i] = orc_step_normal(seed, tag, paths[c], i);
+}
+
 /* Standard normal CDF. */
 double orc_Phi(double x) { return 0.5 * erfc(-x / sqrt(2.0)); }
 
