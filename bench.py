@@ -35,6 +35,7 @@ OU_WEIGHTS = os.path.join(ROOT, "tests", "golden", "ou_mlp_5x50_softplus.sl7w")
 # (s) on an NVIDIA MX150 per path count.  Context only: another machine, and
 # the paper states neither T nor M.
 PAPER_T61_PARALLEL_S = {1_000: 0.268, 50_000: 6.844, 100_000: 14.623, 200_000: 21.545}
+PAPER_T61_CDC_PARALLEL_S = {1_000: 0.062, 50_000: 2.828, 100_000: 5.886, 200_000: 11.527}
 FLOPS_PER_PATH_STEP = 2 * (4 * 64 + 3 * 64 * 64 + 64 * 5)  # 25,728
 PEAK = {"bf16": 2.5e15, "f16": 2.5e15, "bf16x3": 2.5e15, "f16x3": 2.5e15, "f32": 157.3e12,
         "f64": 78.6e12}
@@ -314,6 +315,22 @@ def main():
         log(f"{prec}: {ps / wall_p:.3e} path-steps/s ({wall_p * 1e3:.2f} ms; first call "
             f"{first * 1e3:.1f} ms incl. compile), max rel err {emax_p:.2e}")
 
+    # the 7L-CDC variant: the map only at the marginal collocation points, a
+    # global interpolation per path (no network per path); GBM network map
+    # on the 2^22 x 16 workload
+    cdc = {}
+    for prec in ("f32", "f64"):
+        S.simulate_cdc(pr1, H, prec=prec, seed=g16["seed"])
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st_c, _ = S.simulate_cdc(pr1, H, prec=prec, seed=g16["seed"])
+        dt = (time.perf_counter() - t0) / reps
+        cdc[prec] = {"path_steps_per_s": g16["N"] * g16["M"] / dt, "ms_per_run": dt * 1e3,
+                     "mean_YT": st_c["mean"][0]}
+        log(f"7L-CDC {prec}: {g16['N'] * g16['M'] / dt:.3e} path-steps/s ({dt * 1e3:.2f} ms)")
+
     # the paper's OU experiment (eq. 6.5, 4x50 Softplus network) at the path
     # counts of Table 6.1
     ou = {}
@@ -329,6 +346,21 @@ def main():
                     "mean_YT": st_o["mean"][0], "paper_mx150_s": PAPER_T61_PARALLEL_S[n]}
             log(f"OU 4x50 softplus {prec}: " + ", ".join(
                 f"N={k} {v['ms_per_run']:.3f} ms" for k, v in ou[prec].items()))
+        # the paper's 7L-CDC column of Table 6.1: the same shapes through the CDC variant
+        for prec in ("f32", "f64"):
+            for n in P["path_counts"]:
+                pro = S.Problem(P["model"], P["theta"], P["Y0"], P["T"], P["M"], P["m"], n, K=P["K"])
+                S.simulate_cdc(pro, Hou, prec=prec, seed=P["seed"])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(20):
+                    st_o, _ = S.simulate_cdc(pro, Hou, prec=prec, seed=P["seed"])
+                dt = (time.perf_counter() - t0) / 20
+                ou.setdefault("cdc_" + prec, {})[str(n)] = {
+                    "ms_per_run": dt * 1e3, "path_steps_per_s": n * P["M"] / dt,
+                    "mean_YT": st_o["mean"][0], "paper_mx150_cdc_s": PAPER_T61_CDC_PARALLEL_S[n]}
+            log(f"OU 7L-CDC {prec}: " + ", ".join(
+                f"N={k} {v['ms_per_run']:.3f} ms" for k, v in ou["cdc_" + prec].items()))
         # per-path error at the largest path count against the library's FP64
         # mode (floor 0.5, the path scale: OU paths cross zero)
         n = max(P["path_counts"])
@@ -427,6 +459,7 @@ def main():
         "adjoint_gbm_2p22x16": adj,
         "batched_cir_256": dict(batched, instances=len(prs), path_steps=ps4),
         "piecewise_linear": pwl,
+        "cdc_gbm_2p22x16": cdc,
         "ou_table61_shape": dict(ou, workload=f"OU theta={W.OU_PAPER['theta']}, Y0={W.OU_PAPER['Y0']}, "
                                               f"T={W.OU_PAPER['T']}, M={W.OU_PAPER['M']}, m=5, "
                                               "MLP 5-50x4-5 Softplus") if ou else None,

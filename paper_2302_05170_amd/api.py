@@ -177,6 +177,25 @@ def simulate(pr: Problem, H: Mlp | None = None, prec="f32", seed: int = 42, want
     return (_stats_dict(st) if stats else None), yt
 
 
+def simulate_cdc(pr: Problem, H: Mlp | None = None, prec="f32", seed: int = 42,
+                 want_yt: bool = False, yt: torch.Tensor | None = None, stats: bool = True,
+                 stream=None):
+    """Runs sl7_simulate_cdc (the 7L-CDC variant; prec "f64" or "f32").
+    Returns (stats dict or None, Y_T tensor or None)."""
+    p = _prec(prec)
+    dt = torch.float64 if p == L.F64 else torch.float32
+    if want_yt and yt is None:
+        yt = torch.empty(int(pr.N), dtype=dt, device="cuda")
+    if yt is not None:
+        _check_tensor("yt", yt, dt, (int(pr.N),))
+    st = L.Stats()
+    cp = pr.c()
+    L.check(L.lib().sl7_simulate_cdc(ctypes.byref(cp), H.handle if H is not None else None, p,
+                                     int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(yt),
+                                     ctypes.byref(st) if stats else None, _stream(stream)))
+    return (_stats_dict(st) if stats else None), yt
+
+
 def pwl_compile(H: Mlp, pr: Problem, max_pieces: int = 1 << 16) -> dict:
     """The exact piecewise-linear form of the ReLU network H along Y for
     instance pr (sl7_pwl_compile, host only): breakpoints [P-1], anchors [P],
@@ -325,7 +344,8 @@ def adjoint(pr: Problem, H: Mlp | None = None, prec="f64", seed: int = 42, payof
 class SL7Adjoint(torch.autograd.Function):
     """E[f(Y_T)] as a differentiable function of (Y0, theta): forward runs the
     adjoint sweep once (value and pathwise Greeks); backward scales the stored
-    Greeks by the incoming gradient.
+    Greeks by the incoming gradient.  The value and the gradients take the
+    device and dtype of Y0 and theta.
 
         value = SL7Adjoint.apply(Y0, theta, problem, H, prec, seed, payoff, ckpt)
     """
@@ -337,10 +357,39 @@ class SL7Adjoint(torch.autograd.Function):
                      problem.K, problem.path_offset, problem.instance)
         g = adjoint(pr, H, prec=prec, seed=seed, payoff=payoff, ckpt_every=ckpt)
         ctx.save_for_backward(torch.tensor(g["grad"], dtype=torch.float64))
-        return torch.tensor(g["value"], dtype=torch.float64)
+        ctx.meta = (Y0.device, Y0.dtype, theta.device, theta.dtype)
+        return torch.tensor(g["value"], dtype=Y0.dtype, device=Y0.device)
 
     @staticmethod
     def backward(ctx, gout):
         (grad,) = ctx.saved_tensors
-        gout = gout.to(torch.float64).cpu()
-        return gout * grad[0], gout * grad[1:], None, None, None, None, None, None
+        dev0, dt0, devt, dtt = ctx.meta
+        gout = gout.detach().to(torch.float64).cpu()
+        g_y0 = (gout * grad[0]).to(device=dev0, dtype=dt0)
+        g_th = (gout * grad[1:]).to(device=devt, dtype=dtt)
+        return g_y0, g_th, None, None, None, None, None, None
+
+
+class SL7TrainLoss(torch.autograd.Function):
+    """The training loss of H (mean squared error over all rows of the labels,
+    Algorithm I step 1) as a differentiable function of H's flat parameter
+    vector: forward and backward run on the GPU through sl7_train_grad (the
+    trainer's MFMA forward and backward kernels).  Forward loads `params`
+    into H; the gradient returned has the device and dtype of `params`.
+
+        loss = SL7TrainLoss.apply(params, H, X, Y)
+    """
+
+    @staticmethod
+    def forward(ctx, params, H, X, Y):
+        H.set_params(params.detach().to(torch.float32).cpu().numpy())
+        loss, g = train_grad(H, X, Y)
+        ctx.save_for_backward(g)
+        ctx.meta = (params.device, params.dtype)
+        return torch.tensor(loss, dtype=params.dtype, device=params.device)
+
+    @staticmethod
+    def backward(ctx, gout):
+        (g,) = ctx.saved_tensors
+        dev, dt = ctx.meta
+        return (g.to(device=dev, dtype=dt) * gout.to(device=dev, dtype=dt)), None, None, None

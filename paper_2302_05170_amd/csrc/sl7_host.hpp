@@ -60,7 +60,8 @@ struct Workspace {
   int n_cu = 0;
   DevBuf inst, prefix, order, counter, partials, stats, chunks;
   DevBuf pwl;     // piecewise-linear tables of the instances (PWL modes)
-  Staging stage_inst, stage_pwl;
+  DevBuf cdc;     // per-step tables of the 7L-CDC variant
+  Staging stage_inst, stage_pwl, stage_cdc;
   DevBuf aux[8];  // adjoint checkpoints, trainer buffers, ...
   sl7_stats* stats_host = nullptr;
   int stats_host_n = 0;
@@ -142,6 +143,7 @@ int prepare_instances(const sl7_problem* prs, int n, const Mlp* H, int prec, uin
                       bool pwl_theta = false);
 int launch_instances(const SimArgs& a, int n, int64_t N0, const Mlp* H, int prec,
                      const sl7_plan& plan, hipStream_t stream, Workspace& ws);
+
 int run_instances(const sl7_problem* prs, int n, const Mlp* H, int prec, uint64_t seed,
                   void* YT_dev, const sl7_plan* plan, hipStream_t stream, Workspace& ws);
 int fetch_stats(Workspace& ws, int n, sl7_stats* out, hipStream_t stream);

@@ -208,6 +208,43 @@ def test_autograd_function(S, H):
     assert np.allclose(th.grad.numpy(), 2 * np.array(g["grad"][1:]), rtol=0, atol=1e-15)
 
 
+def test_autograd_function_on_device_tensors(S, H):
+    """Y0 and theta as CUDA tensors (float64 and float32): the value and
+    both gradients come back on their devices and in their dtypes."""
+    pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 8, 5, 8192, K=1.0)
+    g = S.adjoint(pr, H, prec="f64", seed=7, payoff=1, ckpt_every=4)
+    for dt in (torch.float64, torch.float32):
+        Y0 = torch.tensor(1.0, dtype=dt, device="cuda", requires_grad=True)
+        th = torch.tensor([0.3, 0.1], dtype=dt, device="cuda", requires_grad=True)
+        v = S.SL7Adjoint.apply(Y0, th, pr, H, "f64", 7, 1, 4)
+        assert v.is_cuda and v.dtype == dt
+        (3.0 * v).backward()
+        assert Y0.grad.is_cuda and Y0.grad.dtype == dt and th.grad.is_cuda and th.grad.dtype == dt
+        tol = 1e-15 if dt == torch.float64 else 1e-6
+        assert abs(Y0.grad.item() - 3 * g["grad"][0]) <= tol * max(1.0, abs(3 * g["grad"][0]))
+        assert np.allclose(th.grad.double().cpu().numpy(), 3 * np.array(g["grad"][1:]), rtol=tol,
+                           atol=0)
+
+
+def test_training_loss_function_gives_the_weight_gradient(S, Ho):
+    """SL7TrainLoss: the MSE training loss as a function of H's parameters;
+    backward yields the weight gradient from the library's trainer kernels,
+    checked against the oracle's FP64 back-propagation at 1e-4."""
+    H = S.Mlp.load(WEIGHTS)
+    X = W.gbm_features(1024, seed=34).astype(np.float32).astype(np.float64)
+    Y = (Ho.forward(X) * 1.01).astype(np.float32).astype(np.float64)
+    p = torch.tensor(H.params(), device="cuda", requires_grad=True)
+    loss = S.SL7TrainLoss.apply(p, H, torch.tensor(X, dtype=torch.float32, device="cuda"),
+                                torch.tensor(Y, dtype=torch.float32, device="cuda"))
+    (0.5 * loss).backward()
+    lo, dW, db = oracle.mse_loss_and_grads(Ho, X, Y)
+    ref = 0.5 * oracle.flatten(dW, db)
+    assert p.grad.is_cuda and p.grad.dtype == torch.float32
+    assert abs(loss.item() - lo) <= 1e-4 * lo
+    g = p.grad.double().cpu().numpy()
+    assert np.max(np.abs(g - ref)) <= 1e-4 * np.max(np.abs(ref))
+
+
 @pytest.mark.parametrize("payoff", [0, 1])
 def test_piecewise_linear_adjoint_matches_oracle_tangents(S, H, Ho, payoff):
     """The reverse sweep through the compiled piecewise-linear form (slope in
