@@ -19,6 +19,7 @@ import torch
 
 import oracle
 import workloads as W
+from lebesgue import F32_TOL, f32_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -114,7 +115,7 @@ def spanning_instances(prs, n_pick=64):
 @pytest.fixture(scope="module")
 def cir_oracle_paths(S):
     """Oracle Y_T of every path of the spanning instances of the 256-instance
-    CIR workload, at their full path counts."""
+    CIR workload, at their full path counts, and each path's largest |X|."""
     Ho = oracle.load_mlp(CIR_WEIGHTS)
     prs = problems(S, 256)
     ref = {}
@@ -122,7 +123,8 @@ def cir_oracle_paths(S):
         pr = prs[k]
         opr = oracle.Problem(pr.model, pr.theta, pr.Y0, pr.T, pr.M, pr.m, pr.instance)
         y, ncl, nood = oracle.simulate(opr, Ho, 11, np.arange(pr.N))
-        ref[k] = (y, ncl, nood)
+        X = oracle.step_normals(11, oracle.make_tag(0, pr.instance), np.arange(pr.N), pr.M)
+        ref[k] = (y, ncl, nood, np.abs(X).max(axis=1))
     return prs, ref
 
 
@@ -140,7 +142,7 @@ def test_batched_launch_means_match_oracle(S, H, cir_oracle_paths):
     got = S.simulate_batched(prs, H, prec="f32", seed=11, use_graph=True)
     worst = [0.0, 0.0]
     plain = [(0.0, -1, 0.0)] * 2
-    for k, (y, ncl, nood) in ref.items():
+    for k, (y, ncl, nood, _) in ref.items():
         assert got[k]["n"] == prs[k].N
         for j, f in enumerate(oracle.payoffs(y, prs[k].K)):
             e = oracle.estimate(f)
@@ -156,28 +158,56 @@ def test_batched_launch_means_match_oracle(S, H, cir_oracle_paths):
           f"{plain[1][0]:.2e} (instance {plain[1][1]}, mean {plain[1][2]:.3e})")
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5), ("bf16x3", 2e-3)])
+# FP32 absolute term for CIR, per step: four units in the last place of 1.0.
+# The CIR network's inputs are scaled to [-1, 1] and its hidden activations
+# are of order one, so its outputs (collocation values of order ybar,
+# 0.02..0.1) carry absolute FP32 errors of a few 2^-23 whatever their own
+# size, and these add up over the M steps (neighbouring states round alike).
+F32_ATOL_CIR = 4 * 2.0 ** -23
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", None), ("bf16x3", 2e-3)])
 def test_cir_instances_match_oracle(S, H, cir_oracle_paths, prec, tol):
     """Every path of the spanning instances at full size, one single-instance
-    launch each.  Gated with the floor ybar (the mean-reversion level); the
-    error against the floor 1e-3 ybar and the absolute error are printed."""
+    launch each.  F64 and BF16X3: relative error against the floor ybar (the
+    mean-reversion level).  FP32: |error| <= 1e-5 max(|Y|, ybar) + M 4 ulp(1),
+    scaled by the interpolant's Lebesgue function at the path's largest |X|
+    beyond 4 (tests/lebesgue.py).  The errors against the floors ybar and
+    1e-3 ybar and the absolute error are printed."""
     prs, ref = cir_oracle_paths
-    w_ybar = w_small = w_abs = 0.0
-    for k, (y_ref, ncl, nood) in ref.items():
+    w_ybar = w_small = w_abs = w_inner = w_ratio = 0.0
+    n_outer = n_over = 0
+    fails = []
+    for k, (y_ref, ncl, nood, xmax) in ref.items():
         pr = prs[k]
         st, yt = S.simulate(pr, H, prec=prec, seed=11, want_yt=True)
         torch.cuda.synchronize()
         y = yt.double().cpu().numpy()
         d = np.abs(y - y_ref)
-        e = d / np.maximum(np.abs(y_ref), pr.theta[1])
+        floor = np.maximum(np.abs(y_ref), pr.theta[1])
+        e = d / floor
+        if tol is None:
+            bound = (F32_TOL * floor + pr.M * F32_ATOL_CIR) * (f32_bound(pr.m, xmax) / F32_TOL)
+            n_over += int(np.count_nonzero(e > F32_TOL))
+            ratio = d / bound
+        else:
+            ratio = e / tol
         w_ybar = max(w_ybar, e.max())
         w_small = max(w_small, (d / np.maximum(np.abs(y_ref), 1e-3 * pr.theta[1])).max())
         w_abs = max(w_abs, d.max())
-        assert e.max() <= tol, (k, e.max())
+        inner = xmax <= 4.0
+        w_inner = max(w_inner, e[inner].max() if inner.any() else 0.0)
+        n_outer += int(np.count_nonzero(~inner))
+        w_ratio = max(w_ratio, ratio.max())
+        if ratio.max() > 1.0:
+            fails.append((k, float(e.max()), float(ratio.max())))
         if prec == "f64":
             assert st["n_clamped"] == ncl and st["n_out_of_domain"] == nood
     print(f"CIR {prec} over {len(ref)} instances: max err {w_ybar:.2e} (floor ybar), "
-          f"{w_small:.2e} (floor 1e-3 ybar), max abs {w_abs:.2e}")
+          f"{w_inner:.2e} on paths with all |X| <= 4, {n_outer} paths beyond; "
+          f"{w_small:.2e} (floor 1e-3 ybar), max abs {w_abs:.2e}; max err/bound {w_ratio:.2f}"
+          + (f"; {n_over} paths above 1e-5 at floor ybar" if tol is None else ""))
+    assert not fails, fails
 
 
 def test_autotune_returns_valid_plan_and_caches(S, H):
