@@ -218,6 +218,24 @@ int sl7_simulate(const sl7_problem* pr, const sl7_mlp* H, int prec,
 int sl7_simulate_cdc(const sl7_problem* pr, const sl7_mlp* H, int prec, uint64_t seed,
                      void* YT_dev, sl7_stats* stats_host, void* stream);
 
+/* sl7_simulate for callers that cannot allocate device memory: code under
+ * stream (graph) capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same problem, network, prec (every mode but PWL32 / PWL64,
+ * which return SL7_EUNSUPPORTED), seed, YT_dev and plan as sl7_simulate,
+ * same kernels and bit-identical results.  stats_dev: NULL, or a device
+ * sl7_stats that receives the statistics; nothing is copied to the host and
+ * the call never synchronises `stream`.  Scratch: one fixed 16.06 MiB array
+ * per device inside this library (held until the process ends), so
+ * pr->N <= 2^24 (SL7_EINVAL beyond).  H's device copy for prec must already
+ * exist on the current device (any earlier sl7_simulate or sl7_eval_H call
+ * with H and prec makes it; SL7_EINVAL otherwise).  The call allocates no
+ * device or pinned memory.  All calls on one device share the one array:
+ * calls whose device work overlaps (other streams, other threads) race;
+ * order them on one stream. */
+int sl7_simulate_noalloc(const sl7_problem* pr, const sl7_mlp* H, int prec,
+                         uint64_t seed, void* YT_dev, sl7_stats* stats_dev,
+                         const sl7_plan* plan, void* stream);
+
 /* The piecewise-linear form of a ReLU network H for one instance pr (the
  * SL7_PWL32 / SL7_PWL64 modes above), computed on the host in FP64.
  * *n_pieces receives the piece count P.  With brk/anchor/slope/value all

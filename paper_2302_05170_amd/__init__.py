@@ -8,4 +8,4 @@ from ._lib import (BF16, CIR, F16, F32, F64, GBM, OU, PWL32, PWL64, RELU, SOFTPL
                    Sl7Error)
 from .api import (Mlp, PRECISIONS, Problem, SL7Adjoint, SL7TrainLoss, adjoint, autotune,  # noqa: F401
                   autotune_batched, eval_H, gh_nodes, labels, pwl_compile, simulate,
-                  simulate_batched, simulate_cdc, train, train_grad)
+                  simulate_batched, simulate_cdc, simulate_noalloc, stats_from_tensor, train, train_grad)

@@ -55,6 +55,7 @@ SIGNATURES = {
     "sl7_mlp_free": (None, [c_p]),
     "sl7_eval_H": (ctypes.c_int, [c_p, ctypes.c_int, c_p, c_i64, c_p, c_p]),
     "sl7_simulate": (ctypes.c_int, [c_p, c_p, ctypes.c_int, c_u64, c_p, c_p, c_p, c_p]),
+    "sl7_simulate_noalloc": (ctypes.c_int, [c_p, c_p, ctypes.c_int, c_u64, c_p, c_p, c_p, c_p]),
     "sl7_simulate_cdc": (ctypes.c_int, [c_p, c_p, ctypes.c_int, c_u64, c_p, c_p, c_p]),
     "sl7_pwl_compile": (ctypes.c_int, [c_p, c_p, ctypes.c_int, c_p, c_p, c_p, c_p, c_p]),
     "sl7_simulate_batched": (ctypes.c_int, [c_p, ctypes.c_int, c_p, ctypes.c_int, c_u64, c_p, c_p,

@@ -196,6 +196,37 @@ def simulate_cdc(pr: Problem, H: Mlp | None = None, prec="f32", seed: int = 42,
     return (_stats_dict(st) if stats else None), yt
 
 
+STATS_DOUBLES = ctypes.sizeof(L.Stats) // 8
+
+
+def stats_from_tensor(t: torch.Tensor) -> dict:
+    """Statistics dict from the device sl7_stats that simulate_noalloc filled
+    (copies to the host, so it waits for the call's work)."""
+    s = L.Stats.from_buffer_copy(t.cpu().numpy().tobytes())
+    return _stats_dict(s)
+
+
+def simulate_noalloc(pr: Problem, H: Mlp | None = None, prec="f32", seed: int = 42,
+                     yt: torch.Tensor | None = None, stats: torch.Tensor | None = None,
+                     plan: dict | None = None, stream=None) -> None:
+    """Runs sl7_simulate_noalloc with caller-owned device buffers: yt (N
+    values, or None) and stats (a float64 CUDA tensor of STATS_DOUBLES
+    values that receives the sl7_stats, or None).  Enqueues work only; read
+    stats with stats_from_tensor."""
+    p = _prec(prec)
+    dt = torch.float64 if p in (L.F64, L.PWL64) else torch.float32
+    if yt is not None:
+        _check_tensor("yt", yt, dt, (int(pr.N),))
+    if stats is not None:
+        _check_tensor("stats", stats, torch.float64, (STATS_DOUBLES,))
+    pl = _plan(plan)
+    cp = pr.c()
+    L.check(L.lib().sl7_simulate_noalloc(ctypes.byref(cp), H.handle if H is not None else None, p,
+                                         int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(yt), _ptr(stats),
+                                         ctypes.byref(pl) if pl is not None else None,
+                                         _stream(stream)))
+
+
 def pwl_compile(H: Mlp, pr: Problem, max_pieces: int = 1 << 16) -> dict:
     """The exact piecewise-linear form of the ReLU network H along Y for
     instance pr (sl7_pwl_compile, host only): breakpoints [P-1], anchors [P],

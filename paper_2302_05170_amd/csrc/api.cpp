@@ -62,7 +62,15 @@ static void hermite_pair(int m, double x, double& hm, double& hm1) {
 int gh_nodes(int m, double* x, double* w) {
   const double L = 2.0 * std::sqrt((double)m) + 2.0;
   const int grid = 40000;
-  std::vector<double> roots;
+  if (m < 1 || m > kMaxGhNodes) return fail(SL7_EINVAL, "gh_nodes: m=%d outside [1, %d]", m, kMaxGhNodes);
+  // fixed-size root list: no heap allocation (the no-allocation entry point uses this)
+  struct Roots {
+    double v[kMaxGhNodes];
+    int n = 0;
+    int size() const { return n; }
+    void push_back(double x) { if (n < kMaxGhNodes) v[n++] = x; }
+    double operator[](int i) const { return v[i]; }
+  } roots;
   double xp = -L, hp, dummy;
   hermite_pair(m, xp, hp, dummy);
   for (int i = 1; i <= grid && (int)roots.size() < m; ++i) {
@@ -701,6 +709,13 @@ static int persistent_grid(const sl7_plan& plan, int n_cu, int64_t n_items) {
 // memset node (safe to capture into a graph).
 int launch_instances(const SimArgs& a_in, int n, int64_t N0, const Mlp* H, int prec,
                      const sl7_plan& plan, hipStream_t stream, Workspace& ws) {
+  return launch_sequence(a_in, n, N0, H, prec, plan, stream, ws.n_cu, ws.chunks.p,
+                         (sl7_stats*)ws.stats.p);
+}
+
+int launch_sequence(const SimArgs& a_in, int n, int64_t N0, const Mlp* H, int prec,
+                    const sl7_plan& plan, hipStream_t stream, int n_cu, void* chunks,
+                    sl7_stats* stats) {
   SimArgs a = a_in;
   a.grab = plan.grab;
   hipError_t e;
@@ -708,14 +723,14 @@ int launch_instances(const SimArgs& a_in, int n, int64_t N0, const Mlp* H, int p
   if (is_pwl(prec)) {
     e = launch_zero_u64(a.counter, 1, stream);
     if (e != hipSuccess) return hip_fail(e, "zero counter");
-    e = launch_sim_pwl(prec, a, persistent_grid(plan, ws.n_cu, a.n_items), plan.waves_per_block,
+    e = launch_sim_pwl(prec, a, persistent_grid(plan, n_cu, a.n_items), plan.waves_per_block,
                        stream);
     if (e != hipSuccess) return hip_fail(e, "launch piecewise-linear kernel");
   } else if (mfma) {
     a.wpack = H->pack[prec]->p;
     e = launch_zero_u64(a.counter, 1, stream);
     if (e != hipSuccess) return hip_fail(e, "zero counter");
-    e = launch_sim_mfma(prec, H->d.act, a, persistent_grid(plan, ws.n_cu, a.n_items),
+    e = launch_sim_mfma(prec, H->d.act, a, persistent_grid(plan, n_cu, a.n_items),
                         plan.waves_per_block, stream);
     if (e != hipSuccess) return hip_fail(e, "launch fused MFMA kernel");
   } else {
@@ -724,7 +739,7 @@ int launch_instances(const SimArgs& a_in, int n, int64_t N0, const Mlp* H, int p
     e = launch_sim_lane(prec, H ? 1 : 0, H ? H->d.act : 0, a, (N0 + 63) / 64, stream);
     if (e != hipSuccess) return hip_fail(e, "launch per-lane kernel");
   }
-  e = launch_finalize(a.partials, a.inst, n, ws.chunks.p, (sl7_stats*)ws.stats.p, stream);
+  e = launch_finalize(a.partials, a.inst, n, chunks, stats, stream);
   if (e != hipSuccess) return hip_fail(e, "launch finalize");
   return SL7_OK;
 }

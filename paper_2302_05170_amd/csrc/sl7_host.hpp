@@ -15,6 +15,8 @@
 
 namespace sl7 {
 
+constexpr int kMaxGhNodes = 16;  // sl7_gh_nodes accepts m in [1, 16]
+
 int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 int n_theta(int model);
@@ -143,7 +145,13 @@ int prepare_instances(const sl7_problem* prs, int n, const Mlp* H, int prec, uin
                       bool pwl_theta = false);
 int launch_instances(const SimArgs& a, int n, int64_t N0, const Mlp* H, int prec,
                      const sl7_plan& plan, hipStream_t stream, Workspace& ws);
-
+// The same launch sequence with its finalize scratch and statistics given
+// directly (no workspace); enqueues kernels only.
+int launch_sequence(const SimArgs& a, int n, int64_t N0, const Mlp* H, int prec,
+                    const sl7_plan& plan, hipStream_t stream, int n_cu, void* chunks,
+                    sl7_stats* stats);
+int fill_nodes(int m, SimArgs& a, double* x_out);
+void fill_inst(const sl7_problem& pr, const Mlp* H, const double* x, InstDev& I);
 int run_instances(const sl7_problem* prs, int n, const Mlp* H, int prec, uint64_t seed,
                   void* YT_dev, const sl7_plan* plan, hipStream_t stream, Workspace& ws);
 int fetch_stats(Workspace& ws, int n, sl7_stats* out, hipStream_t stream);
