@@ -131,18 +131,21 @@ __device__ __forceinline__ typename H16<P>::v8 pack8(f32x4 lo, f32x4 hi) {
 // per workgroup laid out [slot][lane]: each lane reads its own 16 bytes right
 // before use, so the accumulators and their inputs stay in VGPRs.
 struct BiasLds {
-  const f32x4* p;  // 13 slots: hidden [3][4], head
+  const f32x4* p;  // 17 slots: hidden [3][4], head, then the first-layer weights of Y [4]
   // Keeps the bias reads inside the step loop (otherwise the compiler hoists
   // them into registers, which then have to be copied into the accumulators).
   static __device__ __forceinline__ void pin() { asm volatile("" ::: "memory"); }
   __device__ __forceinline__ f32x4 hid(int l, int b, int lane) const { return p[(4 * l + b) * 64 + lane]; }
   __device__ __forceinline__ f32x4 head(int lane) const { return p[12 * 64 + lane]; }
+  __device__ __forceinline__ f32x4 wy(int b, int lane) const { return p[(13 + b) * 64 + lane]; }
 };
 
-// Copies the 13 bias slots (starting at slot s0 of the packed weights) into
-// LDS; every wave of the workgroup must call it.
+// Copies the 13 bias slots and the 4 first-layer slots that follow them
+// (starting at slot s0 of the packed weights) into LDS; every wave of the
+// workgroup must call it.
+constexpr int kBiasSlots = 17;
 __device__ __forceinline__ BiasLds stage_bias(const u32x4* __restrict__ wp, int s0, f32x4* lds) {
-  for (int i = threadIdx.x; i < 13 * 64; i += blockDim.x)
+  for (int i = threadIdx.x; i < kBiasSlots * 64; i += blockDim.x)
     lds[i] = __builtin_bit_cast(f32x4, wp[s0 * 64 + i]);
   __syncthreads();
   return BiasLds{lds};
@@ -153,8 +156,7 @@ struct NetRegsH {
   typedef typename H16<P>::v8 v8;
   v8 A[3][4][2];  // hidden layers: [layer][out block][K block]
   v8 Ah[2];       // head: [K block]
-  f32x4 wY[4];    // first-layer weight of Y (times its input scale)
-  BiasLds C;      // hidden and head biases
+  BiasLds C;      // hidden and head biases, first-layer weights of Y (times its input scale)
   int lane;
 
   __device__ __forceinline__ void load(const u32x4* __restrict__ wp, int ln, f32x4* lds) {
@@ -169,9 +171,6 @@ struct NetRegsH {
 #pragma unroll
     for (int c = 0; c < 2; ++c) Ah[c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
     C = stage_bias(wp, s, lds);
-    s += 13;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) wY[b] = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
   }
 };
 
@@ -217,11 +216,23 @@ struct Split16<SL7_F16X3> {
   static constexpr int base = SL7_F16;
 };
 
+// x - f32(h), h the FP16 value in the low / high half of hw: one
+// v_fma_mix_f32 (-h * 1 + x, h converted exactly inside the instruction).
+// (The result takes x's register.)
+__device__ __forceinline__ float minus_f16_lo(float x, uint32_t hw) {
+  asm("v_fma_mix_f32 %0, -%1, 1.0, %0 op_sel_hi:[1,0,0]" : "+v"(x) : "v"(hw));
+  return x;
+}
+__device__ __forceinline__ float minus_f16_hi(float x, uint32_t hw) {
+  asm("v_fma_mix_f32 %0, -%1, 1.0, %0 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(x) : "v"(hw));
+  return x;
+}
+
 // The (hi, lo) pair of B operands for eight activations, ReLU applied.
 // BF16: hi is the activation truncated to its upper 16 bits and lo = x - hi
 // (exact in FP32, then rounded to BF16); hi and lo carry the sign of x, so
-// ReLU is a signed 16-bit max of the packed halves.  FP16: ReLU in FP32, hi
-// rounded to nearest, lo = x - hi rounded to nearest.
+// ReLU is a signed 16-bit max of the packed halves.  FP16: hi rounded toward
+// zero, lo = x - hi rounded to nearest, ReLU the same way.
 template <int P, int ACT>
 __device__ __forceinline__ void split8(f32x4 a, f32x4 b, typename Split16<P>::v8& hi,
                                        typename Split16<P>::v8& lo) {
@@ -250,13 +261,20 @@ __device__ __forceinline__ void split8(f32x4 a, f32x4 b, typename Split16<P>::v8
       wh[q] = __builtin_bit_cast(uint32_t, hs);
       wl[q] = __builtin_bit_cast(uint32_t, ls);
     } else {
-      const float x0 = relu_bits(v[2 * q]), x1 = relu_bits(v[2 * q + 1]);
-      const v2 h = __builtin_convertvector((f32x2){x0, x1}, v2);
-      const f32x2 back = __builtin_convertvector(h, f32x2);
-      const float l0 = x0 - back[0], l1 = x1 - back[1];
-      const v2 l = __builtin_convertvector((f32x2){l0, l1}, v2);
-      wh[q] = __builtin_bit_cast(uint32_t, h);
-      wl[q] = __builtin_bit_cast(uint32_t, l);
+      // hi: both values rounded toward zero to FP16 in one instruction, then
+      // ReLU on the packed halves (a negative x gives hi = 0).  lo = x - hi,
+      // exact in FP32, one mixed-precision FMA per value reading hi's half
+      // in place; it has the sign of x (hi was truncated), so the ReLU on
+      // the packed lo clears it exactly when x < 0.
+      const float x0 = v[2 * q], x1 = v[2 * q + 1];
+      const s16x2 hs = __builtin_elementwise_max(
+          __builtin_bit_cast(s16x2, __builtin_amdgcn_cvt_pkrtz(x0, x1)), (s16x2){0, 0});
+      const uint32_t hu = __builtin_bit_cast(uint32_t, hs);
+      const float l0 = minus_f16_lo(x0, hu), l1 = minus_f16_hi(x1, hu);
+      const s16x2 ls = __builtin_elementwise_max(
+          __builtin_bit_cast(s16x2, __builtin_convertvector((f32x2){l0, l1}, v2)), (s16x2){0, 0});
+      wh[q] = hu;
+      wl[q] = __builtin_bit_cast(uint32_t, ls);
     }
   }
   hi = __builtin_bit_cast(typename Split16<P>::v8, wh);
@@ -268,8 +286,7 @@ struct NetRegsX3 {
   typedef typename Split16<P>::v8 v8;
   v8 A[3][4][2];        // hi parts of the hidden-layer weights
   v8 Ah[2];             // hi parts of the head weights
-  f32x4 wY[4];
-  BiasLds C;
+  BiasLds C;            // biases and first-layer weights of Y
   const u32x4* lo;      // LDS: lo parts, hidden [3][4][2] then head [2], [slot][lane]
   int lane;
 
@@ -293,9 +310,7 @@ struct NetRegsX3 {
 #pragma unroll
     for (int c = 0; c < 2; ++c) Ah[c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
     const int s_bias = s;
-    s += 13;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) wY[b] = __builtin_bit_cast(f32x4, wp[(s++) * 64 + lane]);
+    s += kBiasSlots;
     for (int i = threadIdx.x; i < 26 * 64; i += blockDim.x) lo_lds[i] = wp[s * 64 + i];
     lo = lo_lds;
     C = stage_bias(wp, s_bias, lds);  // synchronises the workgroup
@@ -334,6 +349,92 @@ __device__ __forceinline__ f32x4 chain_x3(const NetRegsX3<P>& R, const f32x4 z[4
   y = H16<B>::mfma(R.Ah[1], l1, y);
   y = H16<B>::mfma(R.Ah[0], h0, y);
   return H16<B>::mfma(R.Ah[1], h1, y);
+}
+
+// Two independent 16-path groups (a, b) through the same chain, written so
+// that group b's products of a layer do not depend on group a's epilogue of
+// that layer (nor a's next products on b's epilogue): a wave whose MFMAs are
+// in flight issues its own independent VALU work, so one group's bias, ReLU
+// and split run while the other group's products are computed.  Every value
+// is the one the single-group chain computes.
+template <int P, int ACT>
+__device__ __forceinline__ void chain_x3_pair(const NetRegsX3<P>& R, const f32x4 za[4],
+                                              const f32x4 zb[4], f32x4& ya, f32x4& yb) {
+  BiasLds::pin();
+  typedef typename Split16<P>::v8 v8;
+  constexpr int B = Split16<P>::base;
+  v8 ha0, ha1, la0, la1, hb0, hb1, lb0, lb1;
+  split8<P, ACT>(za[0], za[1], ha0, la0);
+  split8<P, ACT>(za[2], za[3], ha1, la1);
+  split8<P, ACT>(zb[0], zb[1], hb0, lb0);
+  split8<P, ACT>(zb[2], zb[3], hb1, lb1);
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    f32x4 aa[4], ab[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const f32x4 c = R.C.hid(l, b, R.lane);
+      const v8 wl0 = R.Al(l, b, 0), wl1 = R.Al(l, b, 1);
+      aa[b] = H16<B>::mfma(wl0, ha0, c);
+      aa[b] = H16<B>::mfma(wl1, ha1, aa[b]);
+      aa[b] = H16<B>::mfma(R.A[l][b][0], la0, aa[b]);
+      aa[b] = H16<B>::mfma(R.A[l][b][1], la1, aa[b]);
+      aa[b] = H16<B>::mfma(R.A[l][b][0], ha0, aa[b]);
+      aa[b] = H16<B>::mfma(R.A[l][b][1], ha1, aa[b]);
+      ab[b] = H16<B>::mfma(wl0, hb0, c);
+      ab[b] = H16<B>::mfma(wl1, hb1, ab[b]);
+      ab[b] = H16<B>::mfma(R.A[l][b][0], lb0, ab[b]);
+      ab[b] = H16<B>::mfma(R.A[l][b][1], lb1, ab[b]);
+      ab[b] = H16<B>::mfma(R.A[l][b][0], hb0, ab[b]);
+      ab[b] = H16<B>::mfma(R.A[l][b][1], hb1, ab[b]);
+    }
+    split8<P, ACT>(aa[0], aa[1], ha0, la0);
+    split8<P, ACT>(aa[2], aa[3], ha1, la1);
+    split8<P, ACT>(ab[0], ab[1], hb0, lb0);
+    split8<P, ACT>(ab[2], ab[3], hb1, lb1);
+  }
+  const f32x4 c = R.C.head(R.lane);
+  const v8 wl0 = R.Ahl(0), wl1 = R.Ahl(1);
+  ya = H16<B>::mfma(wl0, ha0, c);
+  ya = H16<B>::mfma(wl1, ha1, ya);
+  ya = H16<B>::mfma(R.Ah[0], la0, ya);
+  ya = H16<B>::mfma(R.Ah[1], la1, ya);
+  ya = H16<B>::mfma(R.Ah[0], ha0, ya);
+  ya = H16<B>::mfma(R.Ah[1], ha1, ya);
+  yb = H16<B>::mfma(wl0, hb0, c);
+  yb = H16<B>::mfma(wl1, hb1, yb);
+  yb = H16<B>::mfma(R.Ah[0], lb0, yb);
+  yb = H16<B>::mfma(R.Ah[1], lb1, yb);
+  yb = H16<B>::mfma(R.Ah[0], hb0, yb);
+  yb = H16<B>::mfma(R.Ah[1], hb1, yb);
+}
+
+template <int P, int ACT>
+__device__ __forceinline__ void chain_h_pair(const NetRegsH<P>& R, typename H16<P>::v8 a0,
+                                             typename H16<P>::v8 a1, typename H16<P>::v8 b0,
+                                             typename H16<P>::v8 b1, f32x4& ya, f32x4& yb) {
+  BiasLds::pin();
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    f32x4 aa[4], ab[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const f32x4 c = R.C.hid(l, b, R.lane);
+      aa[b] = H16<P>::mfma(R.A[l][b][0], a0, c);
+      aa[b] = H16<P>::mfma(R.A[l][b][1], a1, aa[b]);
+      ab[b] = H16<P>::mfma(R.A[l][b][0], b0, c);
+      ab[b] = H16<P>::mfma(R.A[l][b][1], b1, ab[b]);
+    }
+    a0 = pack8<P, ACT>(aa[0], aa[1]);
+    a1 = pack8<P, ACT>(aa[2], aa[3]);
+    b0 = pack8<P, ACT>(ab[0], ab[1]);
+    b1 = pack8<P, ACT>(ab[2], ab[3]);
+  }
+  const f32x4 c = R.C.head(R.lane);
+  ya = H16<P>::mfma(R.Ah[0], a0, c);
+  ya = H16<P>::mfma(R.Ah[1], a1, ya);
+  yb = H16<P>::mfma(R.Ah[0], b0, c);
+  yb = H16<P>::mfma(R.Ah[1], b1, yb);
 }
 
 // ------------------------------------------------------------------------
@@ -492,19 +593,105 @@ __device__ __forceinline__ void sim_block(const SimArgs& a, const InstDev& I, in
   block_partial(f0, f1, valid ? clamped : 0, valid ? ood : 0, a.partials + I.part_offset + blk);
 }
 
+// The same block with two groups of 16 paths advanced together (groups t and
+// t + 1, t = 0, 2), their networks evaluated by Net::eval_pair.  Every path
+// takes exactly the arithmetic of sim_block, so the results are identical.
+// The first-layer constants of the block's instance sit in the lane's own
+// LDS slots c0s[64 b + lane] (written and read only by that lane), which
+// leaves their registers to the second group.
+template <class Net>
+__device__ __forceinline__ void sim_block_pair(const SimArgs& a, const InstDev& I, int64_t blk,
+                                               const Net& net, const float xr[4],
+                                               const float lr[4], int lane, int g, int n,
+                                               f32x4* c0s) {
+  const int M = I.M;
+  const uint32_t tag = (uint32_t)I.tag;
+  const bool clamp = I.clamp_zero != 0;
+  const float dlo = I.dom_lo_f, dhi = I.dom_hi_f;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) c0s[64 * b + lane] = *(const f32x4*)(I.c0 + 16 * b + 4 * g);
+  float Yrec = 0.f;
+  long long clamped = 0, ood = 0;
+  for (int t = 0; t < 4; t += 2) {
+    const int64_t gpa = I.path_offset + blk * 64 + 16 * t + n;
+    const int64_t gpb = gpa + 16;
+    float Ya = I.Y0_f, Yb = I.Y0_f;
+    float xa[4] = {0.f, 0.f, 0.f, 0.f}, xb[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int i0 = 0; i0 < M; i0 += 4) {
+      if ((i0 & 15) == 0) {
+        const uint32_t q = (uint32_t)(i0 >> 2) + (uint32_t)g;
+        normals4_f32(philox_step_quad(a.seed, q, gpa, tag), xa);
+        normals4_f32(philox_step_quad(a.seed, q, gpb, tag), xb);
+      }
+      const int src = n + 16 * ((i0 >> 2) & 3);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (i0 + u < M) {
+          const float Xa = __shfl(xa[u], src);
+          const float Xb = __shfl(xb[u], src);
+          if (g == t && (Ya < dlo || Ya > dhi)) ++ood;
+          if (g == t + 1 && (Yb < dlo || Yb > dhi)) ++ood;
+          f32x4 yva, yvb;
+          net.eval_pair(Ya, Yb, c0s + lane, yva, yvb);
+          Ya = interp_rows(Xa, yva, xr, lr);
+          Yb = interp_rows(Xb, yvb, xr, lr);
+          if (clamp) {
+            if (Ya < 0.f) {
+              Ya = 0.f;
+              if (g == t) ++clamped;
+            }
+            if (Yb < 0.f) {
+              Yb = 0.f;
+              if (g == t + 1) ++clamped;
+            }
+          }
+        }
+      }
+    }
+    if (g == t) Yrec = Ya;
+    if (g == t + 1) Yrec = Yb;
+  }
+  const int64_t pl = blk * 64 + lane;
+  const bool valid = pl < I.N;
+  if (a.YT && valid) ((float*)a.YT)[I.yt_offset + pl] = Yrec;
+  const double f0 = valid ? (double)Yrec : 0.0;
+  const double f1 = valid ? fmax((double)Yrec - I.K, 0.0) : 0.0;
+  block_partial(f0, f1, valid ? clamped : 0, valid ? ood : 0, a.partials + I.part_offset + blk);
+}
+
 template <int P, int ACT>
 struct NetH {
   NetRegsH<P> R;
   __device__ __forceinline__ f32x4 eval(float Y, const f32x4 c0[4]) const {
     f32x4 z[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 4; ++b) {
+      const f32x4 w = R.C.wy(b, R.lane);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) z[b][r] = fmaf(Y, R.wY[b][r], c0[b][r]);
+      for (int r = 0; r < 4; ++r) z[b][r] = fmaf(Y, w[r], c0[b][r]);
+    }
     return chain_h<P, ACT>(R, pack8<P, ACT>(z[0], z[1]), pack8<P, ACT>(z[2], z[3]));
   }
   __device__ __forceinline__ f32x4 eval_z0(const f32x4 z[4]) const {
     return chain_h<P, ACT>(R, pack8<P, ACT>(z[0], z[1]), pack8<P, ACT>(z[2], z[3]));
+  }
+  // Two groups; c0: the lane's first-layer constants, block b at c0[64 b] (LDS).
+  static constexpr bool kPair = true;
+  __device__ __forceinline__ void eval_pair(float Ya, float Yb, const f32x4* c0, f32x4& ya,
+                                            f32x4& yb) const {
+    BiasLds::pin();
+    f32x4 za[4], zb[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const f32x4 w = R.C.wy(b, R.lane), c = c0[64 * b];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        za[b][r] = fmaf(Ya, w[r], c[r]);
+        zb[b][r] = fmaf(Yb, w[r], c[r]);
+      }
+    }
+    chain_h_pair<P, ACT>(R, pack8<P, ACT>(za[0], za[1]), pack8<P, ACT>(za[2], za[3]),
+                         pack8<P, ACT>(zb[0], zb[1]), pack8<P, ACT>(zb[2], zb[3]), ya, yb);
   }
 };
 
@@ -523,6 +710,8 @@ struct NetF {
     f32x4 Bv[4] = {act4<ACT>(z[0]), act4<ACT>(z[1]), act4<ACT>(z[2]), act4<ACT>(z[3])};
     return chain_f<ACT>(R, Bv);
   }
+  static constexpr bool kPair = false;
+  __device__ __forceinline__ void eval_pair(float, float, const f32x4*, f32x4&, f32x4&) const {}
 };
 
 template <int P, int ACT>
@@ -531,16 +720,37 @@ struct NetX3 {
   __device__ __forceinline__ f32x4 eval(float Y, const f32x4 c0[4]) const {
     f32x4 z[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 4; ++b) {
+      const f32x4 w = R.C.wy(b, R.lane);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) z[b][r] = fmaf(Y, R.wY[b][r], c0[b][r]);
+      for (int r = 0; r < 4; ++r) z[b][r] = fmaf(Y, w[r], c0[b][r]);
+    }
     return chain_x3<P, ACT>(R, z);
   }
   __device__ __forceinline__ f32x4 eval_z0(const f32x4 z[4]) const { return chain_x3<P, ACT>(R, z); }
+  static constexpr bool kPair = true;
+  __device__ __forceinline__ void eval_pair(float Ya, float Yb, const f32x4* c0, f32x4& ya,
+                                            f32x4& yb) const {
+    BiasLds::pin();
+    f32x4 za[4], zb[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const f32x4 w = R.C.wy(b, R.lane), c = c0[64 * b];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        za[b][r] = fmaf(Ya, w[r], c[r]);
+        zb[b][r] = fmaf(Yb, w[r], c[r]);
+      }
+    }
+    chain_x3_pair<P, ACT>(R, za, zb, ya, yb);
+  }
 };
 
+// c0_lds: 4 x 256 f32x4 of LDS (one 256-slot region per wave) for the
+// two-group blocks; unused by the one-group nets.
 template <class Net>
-__device__ __forceinline__ void sim_persistent(const SimArgs& a, const Net& net) {
+__device__ __forceinline__ void sim_persistent(const SimArgs& a, const Net& net,
+                                               f32x4* c0_lds = nullptr) {
   const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
   float xr[4], lr[4];
   lane_rows(a, a.m, g, xr, lr);
@@ -551,7 +761,10 @@ __device__ __forceinline__ void sim_persistent(const SimArgs& a, const Net& net)
     for (uint64_t item = item0; item < end; ++item) {
       int64_t blk;
       const InstDev* I = locate(a, item, blk);
-      sim_block(a, *I, blk, net, xr, lr, lane, g, n);
+      if constexpr (Net::kPair)
+        sim_block_pair(a, *I, blk, net, xr, lr, lane, g, n, c0_lds + (threadIdx.x >> 6) * 256);
+      else
+        sim_block(a, *I, blk, net, xr, lr, lane, g, n);
     }
   }
 }
@@ -559,24 +772,26 @@ __device__ __forceinline__ void sim_persistent(const SimArgs& a, const Net& net)
 template <int P, int ACT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_sim_mfma_h(SimArgs a) {
-  __shared__ f32x4 bias_lds[13 * 64];
+  __shared__ f32x4 bias_lds[kBiasSlots * 64];
+  __shared__ f32x4 c0_lds[4 * 256];
   NetH<P, ACT> net;
   net.R.load((const u32x4*)a.wpack, threadIdx.x & 63, bias_lds);
-  sim_persistent(a, net);
+  sim_persistent(a, net, c0_lds);
 }
 
 template <int P, int ACT>
 __global__ __launch_bounds__(256) void k_sim_mfma_x3(SimArgs a) {
-  __shared__ f32x4 bias_lds[13 * 64];
+  __shared__ f32x4 bias_lds[kBiasSlots * 64];
   __shared__ u32x4 lo_lds[26 * 64];
+  __shared__ f32x4 c0_lds[4 * 256];
   NetX3<P, ACT> net;
   net.R.load((const u32x4*)a.wpack, threadIdx.x & 63, bias_lds, lo_lds);
-  sim_persistent(a, net);
+  sim_persistent(a, net, c0_lds);
 }
 
 template <int ACT>
 __global__ __launch_bounds__(256) void k_sim_mfma_f(SimArgs a) {
-  __shared__ f32x4 bias_lds[13 * 64];
+  __shared__ f32x4 bias_lds[kBiasSlots * 64];
   NetF<ACT> net;
   net.R.load((const u32x4*)a.wpack, threadIdx.x & 63, bias_lds);
   sim_persistent(a, net);
@@ -644,7 +859,7 @@ template <int P, int ACT>
 __global__ __launch_bounds__(256) void k_eval_mfma_h(const void* wpack, const float* w0n,
                                                      const float* c0n, int d_in, int m,
                                                      const float* in, int64_t B, float* out) {
-  __shared__ f32x4 bias_lds[13 * 64];
+  __shared__ f32x4 bias_lds[kBiasSlots * 64];
   NetH<P, ACT> net;
   net.R.load((const u32x4*)wpack, threadIdx.x & 63, bias_lds);
   eval_rows(net, w0n, c0n, d_in, m, in, B, out);
@@ -654,7 +869,7 @@ template <int P, int ACT>
 __global__ __launch_bounds__(256) void k_eval_mfma_x3(const void* wpack, const float* w0n,
                                                       const float* c0n, int d_in, int m,
                                                       const float* in, int64_t B, float* out) {
-  __shared__ f32x4 bias_lds[13 * 64];
+  __shared__ f32x4 bias_lds[kBiasSlots * 64];
   __shared__ u32x4 lo_lds[26 * 64];
   NetX3<P, ACT> net;
   net.R.load((const u32x4*)wpack, threadIdx.x & 63, bias_lds, lo_lds);
@@ -665,7 +880,7 @@ template <int ACT>
 __global__ __launch_bounds__(256) void k_eval_mfma_f(const void* wpack, const float* w0n,
                                                      const float* c0n, int d_in, int m,
                                                      const float* in, int64_t B, float* out) {
-  __shared__ f32x4 bias_lds[13 * 64];
+  __shared__ f32x4 bias_lds[kBiasSlots * 64];
   NetF<ACT> net;
   net.R.load((const u32x4*)wpack, threadIdx.x & 63, bias_lds);
   eval_rows(net, w0n, c0n, d_in, m, in, B, out);
