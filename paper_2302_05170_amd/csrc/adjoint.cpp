@@ -91,7 +91,7 @@ std::vector<T> lane_layout(const Mlp& H) {
 
 template <typename T>
 int upload_lane(const Mlp& H, std::unique_ptr<DevBuf>& net, std::unique_ptr<DevBuf>& wth) {
-  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "FP32 or FP64");
+  static_assert(sizeof(T) == 8, "the lane sweep of a network runs in FP64");
   const int nth = H.d.d_in - 2;
   std::vector<double> wt((size_t)nth * 64);  // FP64 for both T
   for (int k = 0; k < nth; ++k)
@@ -108,22 +108,59 @@ int upload_lane(const Mlp& H, std::unique_ptr<DevBuf>& net, std::unique_ptr<DevB
   return SL7_OK;
 }
 
+// The LDS image of the MFMA sweep (slot map in sl7_adjoint.hpp), FP32.
+std::vector<float> mfma_image(const Mlp& H) {
+  std::vector<float> v((size_t)kAmC0 * 64 * 4, 0.f);
+  auto put = [&](int s, int lane, int e, double x) { v[((size_t)s * 64 + lane) * 4 + e] = (float)x; };
+  const int m = H.d.m, nth = H.d.d_in - 2;
+  for (int lane = 0; lane < 64; ++lane) {
+    const int g = lane / 16, i = lane % 16;
+    for (int e = 0; e < 4; ++e) {
+      for (int l = 0; l < 3; ++l)
+        for (int b = 0; b < 4; ++b) {
+          for (int q = 0; q < 4; ++q) {
+            put(kAmFwd + 16 * l + 4 * b + q, lane, e, H.W(l + 1, 16 * b + i, 16 * q + 4 * g + e));
+            put(kAmRev + 16 * l + 4 * b + q, lane, e, H.W(l + 1, 16 * q + 4 * g + e, 16 * b + i));
+          }
+          put(kAmBias + 4 * l + b, lane, e, H.b(l + 1, 16 * b + 4 * g + e));
+        }
+      const int j = 4 * g + e;
+      for (int q = 0; q < 4; ++q) put(kAmHead + q, lane, e, i < m ? H.W(4, i, 16 * q + 4 * g + e) : 0.f);
+      put(kAmBias + 12, lane, e, j < m ? H.b(4, j) : 0.f);
+      for (int b = 0; b < 4; ++b) {
+        const int u = 16 * b + 4 * g + e;
+        put(kAmRevH + b, lane, e, j < m ? H.W(4, j, 16 * b + i) : 0.f);
+        put(kAmWy + b, lane, e, (double)H.W(0, u, 0) * H.d.in_scale[0]);
+        for (int k = 0; k < nth && k < 3; ++k)
+          put(kAmWth + 4 * k + b, lane, e, (double)H.W(0, u, 2 + k) * H.d.in_scale[2 + k]);
+      }
+    }
+  }
+  return v;
+}
+
 }  // namespace
 
 namespace sl7 {
 
-int upload_lane_layout(const Mlp& H, int prec, std::unique_ptr<DevBuf>& net,
-                       std::unique_ptr<DevBuf>& wth) {
-  return prec == SL7_F64 ? upload_lane<double>(H, net, wth) : upload_lane<float>(H, net, wth);
+int upload_lane_layout(const Mlp& H, std::unique_ptr<DevBuf>& net, std::unique_ptr<DevBuf>& wth) {
+  return upload_lane<double>(H, net, wth);
 }
 
-// Lane layout of the network in the sweep's precision plus the first-layer
-// weights of theta (times their input scales), for the adjoint kernels.
+// FP64: the lane layout of the network plus the first-layer weights of theta
+// (times their input scales); FP32: the MFMA sweep's LDS image.
 int Mlp::ensure_adjoint(int prec) {
   int rc = ensure_device(SL7_F64);  // binds the handle to the device; builds the FP64 layout
   if (rc || prec == SL7_F64) return rc;
   std::lock_guard<std::mutex> lk(mu);
-  return lane32 && wth32 ? SL7_OK : upload_lane<float>(*this, lane32, wth32);
+  if (adj_img) return SL7_OK;
+  const std::vector<float> v = mfma_image(*this);
+  adj_img.reset(new DevBuf());
+  rc = adj_img->reserve(v.size() * sizeof(float));
+  if (rc) { adj_img.reset(); return rc; }
+  const hipError_t e = hipMemcpy(adj_img->p, v.data(), v.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { adj_img.reset(); return hip_fail(e, "upload the adjoint's MFMA image"); }
+  return SL7_OK;
 }
 
 }  // namespace sl7
@@ -184,9 +221,11 @@ extern "C" int sl7_adjoint(const sl7_problem* pr, const sl7_mlp* Hc, int prec, u
     a.net = sa.wpack;  // the piecewise-linear tables with theta derivatives
   } else if (H) {
     mode = H->d.act == SL7_RELU ? 1 : 3;
-    a.net = prec == SL7_F64 ? H->lane64->p : H->lane32->p;
-    a.wtheta = prec == SL7_F64 ? H->wth64->p : H->wth32->p;
-    a.c0 = instp + (prec == SL7_F64 ? offsetof(InstDev, c0d) : offsetof(InstDev, c0));
+    if (prec == SL7_F64) {
+      a.net = H->lane64->p;
+      a.wtheta = H->wth64->p;
+      a.c0 = instp + offsetof(InstDev, c0d);
+    }
   }
   char* w = (char*)ws_dev;
   a.ckpt_buf = w + Lw.ckpt;
@@ -196,7 +235,10 @@ extern "C" int sl7_adjoint(const sl7_problem* pr, const sl7_mlp* Hc, int prec, u
   a.per_path = per_path_dev;
   a.seed = seed;
   const int64_t nb = (pr->N + 63) / 64;
-  hipError_t e = launch_adjoint(prec, mode, a, nb, s);
+  // FP32 with a network: the sweep on MFMA; otherwise one path per lane
+  hipError_t e = H && prec == SL7_F32
+                     ? launch_adjoint_mfma(H->d.act, a, H->adj_img->p, nb, ws.n_cu, s)
+                     : launch_adjoint(prec, mode, a, nb, s);
   if (e != hipSuccess) return hip_fail(e, "launch adjoint");
   double res[12];
   e = hipMemcpyAsync(res, a.result, sizeof(res), hipMemcpyDeviceToHost, s);

@@ -280,9 +280,8 @@ void Mlp::drop_device() {
   for (auto& p : pack) p.reset();
   net64.reset();
   lane64.reset();
-  lane32.reset();
   wth64.reset();
-  wth32.reset();
+  adj_img.reset();
   w0full.reset();
   w0n.reset();
   c0n.reset();
@@ -426,7 +425,7 @@ int Mlp::ensure_device(int prec) {
   if (prec == SL7_F64) {
     if (net64 && lane64) return SL7_OK;
     if (!lane64) {
-      rc = upload_lane_layout(*this, SL7_F64, lane64, wth64);
+      rc = upload_lane_layout(*this, lane64, wth64);
       if (rc) return rc;
     }
     if (net64) return SL7_OK;

@@ -14,7 +14,9 @@
 // derivatives compiled on the host).  Starts from lambda = f'(Y_T); a CIR
 // step clamped to 0 passes no gradient.
 // thetabar accumulates in FP64.  One path per lane, one 64-path block per
-// workgroup; block sums in a fixed order.
+// workgroup; block sums in a fixed order.  Runs the analytic map (FP64,
+// FP32), the network in FP64 and the piecewise-linear form; the FP32 sweep
+// through a network runs on MFMA (k_adjoint_mfma.hip).
 #include <hip/hip_runtime.h>
 
 #include "block_grid.hpp"
@@ -156,15 +158,13 @@ constexpr int state_words() { return MODE == kAdjNet ? 8 : (MODE == kAdjPwl ? 1 
 // segment), and the reverse step, which needs no evaluation of the map.
 // Forward pass and recomputation share one loop, so each evaluation routine
 // appears once in the code.
-// Waves per SIMD the register allocation aims at.  The network sweep keeps
-// a 64-entry activation vector per lane; measured fastest: three waves per
-// SIMD in FP32 and two in FP64 (one wave alone cannot keep the FP64 FMA
-// pipe busy, even with no spills), and one fewer for Softplus, which also
-// keeps the cotangent vector.
+// Waves per SIMD the register allocation aims at.  The FP64 network sweep
+// keeps a 64-entry activation vector per lane; measured fastest: two waves
+// per SIMD (one wave alone cannot keep the FP64 FMA pipe busy, even with no
+// spills), and one for Softplus, which also keeps the cotangent vector.
 template <typename T, int MODE>
 constexpr int adjoint_waves() {
-  return MODE == kAdjNet ? (sizeof(T) == 8 ? 2 : 3)
-                         : (MODE == kAdjNetSoftplus ? (sizeof(T) == 8 ? 1 : 2) : 1);
+  return MODE == kAdjNet ? 2 : (MODE == kAdjNetSoftplus ? 1 : 1);
 }
 
 template <typename T, int MODE>
@@ -332,12 +332,16 @@ hipError_t launch_adjoint(int prec, int mode, const AdjArgs& a, int64_t n_blocks
         : mode == kAdjPwl         ? launch_one<double, kAdjPwl>(a, n_blocks, lds, s)
                                   : launch_one<double, kAdjAnalytic>(a, n_blocks, lds, s);
   } else {
-    e = mode == kAdjNet           ? launch_one<float, kAdjNet>(a, n_blocks, lds, s)
-        : mode == kAdjNetSoftplus ? launch_one<float, kAdjNetSoftplus>(a, n_blocks, lds, s)
-        : mode == kAdjPwl         ? launch_one<float, kAdjPwl>(a, n_blocks, lds, s)
-                                  : launch_one<float, kAdjAnalytic>(a, n_blocks, lds, s);
+    // (an FP32 sweep through a network runs on MFMA: k_adjoint_mfma.hip)
+    if (is_net(mode)) return hipErrorInvalidValue;
+    e = mode == kAdjPwl ? launch_one<float, kAdjPwl>(a, n_blocks, lds, s)
+                        : launch_one<float, kAdjAnalytic>(a, n_blocks, lds, s);
   }
   if (e != hipSuccess) return e;
+  return launch_adjoint_finalize(a, n_blocks, s);
+}
+
+hipError_t launch_adjoint_finalize(const AdjArgs& a, int64_t n_blocks, hipStream_t s) {
   hipLaunchKernelGGL(k_adjoint_finalize, dim3(1), dim3(256), 0, s, a.partials, n_blocks,
                      a.inst_N, a.result);
   return hipGetLastError();

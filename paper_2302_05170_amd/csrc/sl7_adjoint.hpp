@@ -35,5 +35,28 @@ size_t adjoint_lds_bytes(int prec, int mode, int ckpt);
 // 1 piecewise-linear, 0 analytic and Softplus).
 int adjoint_state_words(int mode);
 hipError_t launch_adjoint(int prec, int mode, const AdjArgs& a, int64_t n_blocks, hipStream_t s);
+// Means and standard errors of the block partials into a.result.
+hipError_t launch_adjoint_finalize(const AdjArgs& a, int64_t n_blocks, hipStream_t s);
+
+// The sweep with the network on MFMA (FP32 operands), ReLU or Softplus;
+// img: the LDS image below (kAmC0 slots), n_cu: compute units.
+hipError_t launch_adjoint_mfma(int act, const AdjArgs& a, const void* img, int64_t n_blocks,
+                               int n_cu, hipStream_t s);
+
+// Slots of the MFMA sweep's LDS image (one 16-byte slot per lane, 64 lanes
+// per slot).  The host fills slots [0, kAmC0); the kernel fills the
+// instance's first-layer constant.  Lane (g, i) = (lane / 16, lane % 16);
+// element e of a slot.
+//   kAmFwd   + 16 l + 4 b + q : W_{l+1}[16 b + i][16 q + 4 g + e]
+//   kAmHead  + q              : W_head[i][16 q + 4 g + e]          (i < m)
+//   kAmBias  + 4 l + b        : b_{l+1}[16 b + 4 g + e]; kAmBias + 12: b_head[4 g + e]
+//   kAmWy    + b              : W_0[16 b + 4 g + e][Y] x input scale of Y
+//   kAmRev   + 16 l + 4 b + q : W_{l+1}[16 q + 4 g + e][16 b + i]
+//   kAmRevH  + b              : W_head[4 g + e][16 b + i]          (4 g + e < m)
+//   kAmWth   + 4 k + b        : W_0[16 b + 4 g + e][theta_k] x its input scale
+//   kAmC0    + b              : first-layer constant (bias, dt and theta folded)
+constexpr int kAmFwd = 0, kAmHead = 48, kAmBias = 52, kAmWy = 65, kAmRev = 69, kAmRevH = 117,
+              kAmWth = 121, kAmC0 = 133, kAmSlots = 137;
+static_assert(kAmWy + 4 == kAmRev && kAmWth + 12 == kAmC0, "slot map");
 
 }  // namespace sl7

@@ -113,7 +113,8 @@ struct Mlp {
   std::unique_ptr<DevBuf> net64, w0full, w0n, c0n;
   // one-path-per-lane layouts (net_lane.hpp) in FP64 / FP32 and the theta
   // weights of the first layer (FP64) for the lane kernels and the adjoint
-  std::unique_ptr<DevBuf> lane64, lane32, wth64, wth32;
+  std::unique_ptr<DevBuf> lane64, wth64;  // FP64 lane layout of the adjoint sweep
+  std::unique_ptr<DevBuf> adj_img;        // LDS image of the FP32 MFMA adjoint sweep
   // compiled piecewise-linear forms by instance (model, dt, theta); cleared
   // with the device copies whenever the parameters change
   std::map<std::array<double, 5>, std::shared_ptr<PwlPieces>> pwl_cache;
@@ -130,10 +131,9 @@ struct Mlp {
 };
 
 int64_t n_params_of(const sl7_mlp_desc& d);
-// Builds and uploads H's lane layout in FP64 (prec SL7_F64) or FP32 and its
-// theta weights; the caller holds H.mu.
-int upload_lane_layout(const Mlp& H, int prec, std::unique_ptr<DevBuf>& net,
-                       std::unique_ptr<DevBuf>& wth);
+// Builds and uploads H's FP64 lane layout (FP64 adjoint sweep and FP64
+// simulation) and its theta weights; the caller holds H.mu.
+int upload_lane_layout(const Mlp& H, std::unique_ptr<DevBuf>& net, std::unique_ptr<DevBuf>& wth);
 int check_desc(const sl7_mlp_desc* d);
 int check_problem(const sl7_problem* pr, const Mlp* H, int prec, const char* name);
 int check_plan(const sl7_plan* p);
