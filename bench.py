@@ -183,7 +183,7 @@ def main():
     ap.add_argument("--profile-run", default=None,
                     help="only run the default workload in this precision (plus a 256 MiB "
                          "calibration copy) for rocprofv3; prints no JSON.  adjoint_f64 / "
-                         "adjoint_f32: the adjoint workload's sweep instead")
+                         "adjoint_f32 / adjoint_bf16x3: the adjoint workload's sweep instead")
     ap.add_argument("--grab", type=int, default=None,
                     help="with --profile-run: 64-path blocks per work-queue grab (default plan "
                          "otherwise)")
@@ -254,15 +254,33 @@ def main():
     ga = W.CONFIGS["gbm_adjoint_2p22x16"]
     pr3 = S.Problem(ga["model"], ga["theta"], ga["Y0"], ga["T"], ga["M"], ga["m"], ga["N"], K=ga["K"])
     adj = {}
-    for prec in ("f64", "f32", "pwl64", "pwl32"):
+    # algorithmic network flops of one sweep: forward pass over all M steps,
+    # recomputation of every segment but the last, and the reverse products
+    # (head transpose, three hidden transposes, first-layer reduction for Y
+    # and theta) at every step
+    nseg = -(-ga["M"] // ga["ckpt"])
+    fwd_evals = ga["M"] + (nseg - 1) * ga["ckpt"]
+    rev_flops = 2 * (64 * ga["m"] + 3 * 64 * 64 + 64 * (1 + 2))  # Y and (sigma, mu)
+    adj_flops = ga["N"] * (fwd_evals * FLOPS_PER_PATH_STEP + ga["M"] * rev_flops)
+    for prec in ("f64", "f32", "bf16x3", "pwl64", "pwl32"):
         S.adjoint(pr3, H, prec=prec, seed=ga["seed"], payoff=1, ckpt_every=ga["ckpt"])
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g = S.adjoint(pr3, H, prec=prec, seed=ga["seed"], payoff=1, ckpt_every=ga["ckpt"])
-        dt = time.perf_counter() - t0
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            g = S.adjoint(pr3, H, prec=prec, seed=ga["seed"], payoff=1, ckpt_every=ga["ckpt"])
+            ts.append(time.perf_counter() - t0)
+        dt = sorted(ts)[1]
         adj[prec] = {"s_per_greek": dt / len(g["grad"]), "seconds": dt, "greeks": g["grad"],
                      "greeks_se": g["grad_se"]}
-        log(f"adjoint {prec}: {dt:.3f} s for {len(g['grad'])} Greeks {g['grad']}")
+        if prec in ("f32", "bf16x3"):
+            adj[prec]["alg_tflops"] = adj_flops / dt / 1e12
+            adj[prec]["frac_of_dtype_peak"] = adj_flops / dt / PEAK[prec]
+        log(f"adjoint {prec}: {dt:.4f} s (median of 3) for {len(g['grad'])} Greeks {g['grad']}")
+    for prec in adj:
+        if prec != "f64":
+            adj[prec]["max_rel_err_of_greeks_vs_f64"] = max(
+                abs(a - b) / abs(b) for a, b in zip(adj[prec]["greeks"], adj["f64"]["greeks"]))
 
     # batched: 256 uneven CIR instances in one persistent launch, graph replays
     Hc = S.Mlp.load(CIR_WEIGHTS)
@@ -376,7 +394,7 @@ def main():
         # the Softplus network, at the largest path count
         n = max(P["path_counts"])
         pro = S.Problem(P["model"], P["theta"], P["Y0"], P["T"], P["M"], P["m"], n, K=P["K"])
-        for prec in ("f64", "f32"):
+        for prec in ("f64", "f32", "bf16x3"):
             S.adjoint(pro, Hou, prec=prec, seed=P["seed"], payoff=1, ckpt_every=4)
             torch.cuda.synchronize()
             t0 = time.perf_counter()

@@ -281,16 +281,18 @@ typedef struct {
  * depend on H) plus block sums.  0 for bad arguments. */
 size_t sl7_adjoint_ws_bytes(const sl7_problem* pr, int prec, int ckpt_every);
 
-/* H == NULL: analytic map (GBM, OU).  prec: SL7_F64 or SL7_F32 (the
- * accumulation of the theta-gradients is FP64 in both), with the analytic
+/* H == NULL: analytic map (GBM, OU).  prec: SL7_F64, SL7_F32 or SL7_BF16X3
+ * (the accumulation of the theta-gradients is FP64 in all), with the analytic
  * map, a ReLU network or a Softplus network (whose reverse pass recomputes
  * each hidden layer's pre-activation from Y_i for the logistic derivative).
  * In SL7_F32 a network's sweep runs on MFMA with FP32 operands, forward and
- * transposed products over 16-path tiles (the forward half takes the
- * arithmetic of sl7_simulate's FP32 kernel, so f per path equals the payoff
- * of its Y_T); SL7_F64 runs one path per lane on the FP64 vector units;
- * for a ReLU network also SL7_PWL64 / SL7_PWL32, which back-propagate
- * through the network's
+ * transposed products over 16-path tiles; SL7_BF16X3 (a network only) runs
+ * the same sweep with three-pass split BF16 products (hi*hi + hi*lo + lo*hi
+ * of weights and of activations or cotangents, FP32 accumulation).  In both
+ * the forward half takes the arithmetic of sl7_simulate's kernel of that
+ * precision, so f per path equals the payoff of its Y_T.  SL7_F64 runs one
+ * path per lane on the FP64 vector units.  For a ReLU network also
+ * SL7_PWL64 / SL7_PWL32, which back-propagate through the network's
  * piecewise-linear form: per piece the slope in Y and dy_j/dtheta_k (the
  * piece's activation pattern held fixed, as back-propagation holds its ReLU
  * masks) are compiled on the host in FP64 with the pieces.  ws_dev: caller's

@@ -139,6 +139,80 @@ std::vector<float> mfma_image(const Mlp& H) {
   return v;
 }
 
+uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+float bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// The LDS image of the split-BF16 sweep (slot map in sl7_adjoint.hpp):
+// weights as hi = rn(w) and lo = rn(w - hi) in BF16, the rest FP32.
+std::vector<uint32_t> mfma_image_x3(const Mlp& H) {
+  std::vector<uint32_t> v((size_t)kXC0 * 64 * 4, 0u);
+  auto put_f = [&](int s, int lane, int e, double x) {
+    const float f = (float)x;
+    std::memcpy(&v[((size_t)s * 64 + lane) * 4 + e], &f, 4);
+  };
+  auto half = [&](int s, int lane, int e, uint16_t b) {
+    uint32_t& w = v[((size_t)s * 64 + lane) * 4 + e / 2];
+    w = e % 2 == 0 ? (w & 0xffff0000u) | b : (w & 0x0000ffffu) | ((uint32_t)b << 16);
+  };
+  auto put_w = [&](int s_hi, int s_lo, int lane, int e, float w) {
+    const uint16_t hb = bf16_rne(w);
+    half(s_hi, lane, e, hb);
+    half(s_lo, lane, e, bf16_rne(w - bf16_value(hb)));
+  };
+  auto feat = [](int c, int g, int e) { return 16 * (2 * c + e / 4) + 4 * g + e % 4; };
+  const int m = H.d.m, nth = H.d.d_in - 2;
+  for (int lane = 0; lane < 64; ++lane) {
+    const int g = lane / 16, i = lane % 16;
+    for (int e = 0; e < 8; ++e) {
+      for (int l = 0; l < 3; ++l)
+        for (int b = 0; b < 4; ++b)
+          for (int c = 0; c < 2; ++c) {
+            const int s = 8 * l + 2 * b + c, f = feat(c, g, e);
+            put_w(kXFwdH + s, kXFwdL + s, lane, e, H.W(l + 1, 16 * b + i, f));
+            put_w(kXRevH + s, kXRevL + s, lane, e, H.W(l + 1, f, 16 * b + i));
+          }
+      for (int c = 0; c < 2; ++c)
+        put_w(kXFwdH + 24 + c, kXFwdL + 24 + c, lane, e, i < m ? H.W(4, i, feat(c, g, e)) : 0.f);
+      const int j = feat(0, g, e);
+      for (int b = 0; b < 4; ++b)
+        put_w(kXRevH + 24 + b, kXRevL + 24 + b, lane, e, j < m ? H.W(4, j, 16 * b + i) : 0.f);
+    }
+    for (int r = 0; r < 4; ++r) {
+      for (int l = 0; l < 3; ++l)
+        for (int b = 0; b < 4; ++b) put_f(kXBias + 4 * l + b, lane, r, H.b(l + 1, 16 * b + 4 * g + r));
+      const int j = 4 * g + r;
+      put_f(kXBias + 12, lane, r, j < m ? H.b(4, j) : 0.f);
+      for (int b = 0; b < 4; ++b) {
+        const int u = 16 * b + 4 * g + r;
+        put_f(kXWy + b, lane, r, (double)H.W(0, u, 0) * H.d.in_scale[0]);
+        for (int k = 0; k < nth && k < 3; ++k)
+          put_f(kXWth + 4 * k + b, lane, r, (double)H.W(0, u, 2 + k) * H.d.in_scale[2 + k]);
+      }
+    }
+  }
+  return v;
+}
+
+int upload_image(std::unique_ptr<DevBuf>& buf, const void* src, size_t bytes) {
+  buf.reset(new DevBuf());
+  int rc = buf->reserve(bytes);
+  if (rc) { buf.reset(); return rc; }
+  const hipError_t e = hipMemcpy(buf->p, src, bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { buf.reset(); return hip_fail(e, "upload the adjoint's MFMA image"); }
+  return SL7_OK;
+}
+
 }  // namespace
 
 namespace sl7 {
@@ -148,19 +222,19 @@ int upload_lane_layout(const Mlp& H, std::unique_ptr<DevBuf>& net, std::unique_p
 }
 
 // FP64: the lane layout of the network plus the first-layer weights of theta
-// (times their input scales); FP32: the MFMA sweep's LDS image.
+// (times their input scales); FP32 and BF16X3: the MFMA sweep's LDS image.
 int Mlp::ensure_adjoint(int prec) {
   int rc = ensure_device(SL7_F64);  // binds the handle to the device; builds the FP64 layout
   if (rc || prec == SL7_F64) return rc;
   std::lock_guard<std::mutex> lk(mu);
+  if (prec == SL7_BF16X3) {
+    if (adj_img_x3) return SL7_OK;
+    const std::vector<uint32_t> v = mfma_image_x3(*this);
+    return upload_image(adj_img_x3, v.data(), v.size() * sizeof(uint32_t));
+  }
   if (adj_img) return SL7_OK;
   const std::vector<float> v = mfma_image(*this);
-  adj_img.reset(new DevBuf());
-  rc = adj_img->reserve(v.size() * sizeof(float));
-  if (rc) { adj_img.reset(); return rc; }
-  const hipError_t e = hipMemcpy(adj_img->p, v.data(), v.size() * sizeof(float), hipMemcpyHostToDevice);
-  if (e != hipSuccess) { adj_img.reset(); return hip_fail(e, "upload the adjoint's MFMA image"); }
-  return SL7_OK;
+  return upload_image(adj_img, v.data(), v.size() * sizeof(float));
 }
 
 }  // namespace sl7
@@ -176,8 +250,10 @@ extern "C" int sl7_adjoint(const sl7_problem* pr, const sl7_mlp* Hc, int prec, u
   Mlp* H = const_cast<Mlp*>(reinterpret_cast<const Mlp*>(Hc));
   int rc = check_problem(pr, H, prec, "pr");
   if (rc) return rc;
-  if (prec != SL7_F64 && prec != SL7_F32 && !is_pwl(prec))
-    return fail(SL7_EUNSUPPORTED, "the adjoint runs in F64, F32, PWL64 or PWL32");
+  if (prec != SL7_F64 && prec != SL7_F32 && !is_pwl(prec) && prec != SL7_BF16X3)
+    return fail(SL7_EUNSUPPORTED, "the adjoint runs in F64, F32, BF16X3, PWL64 or PWL32");
+  if (prec == SL7_BF16X3 && !H)
+    return fail(SL7_EUNSUPPORTED, "the BF16X3 adjoint needs a network (its products run on MFMA)");
   if (payoff != 0 && payoff != 1) return fail(SL7_EINVAL, "payoff=%d must be 0 (Y_T) or 1 (call)", payoff);
   if (ckpt_every < 1 || ckpt_every > 32) return fail(SL7_EINVAL, "ckpt_every=%d outside [1, 32]", ckpt_every);
   if (!out) return fail(SL7_EINVAL, "out is NULL");
@@ -235,10 +311,13 @@ extern "C" int sl7_adjoint(const sl7_problem* pr, const sl7_mlp* Hc, int prec, u
   a.per_path = per_path_dev;
   a.seed = seed;
   const int64_t nb = (pr->N + 63) / 64;
-  // FP32 with a network: the sweep on MFMA; otherwise one path per lane
-  hipError_t e = H && prec == SL7_F32
-                     ? launch_adjoint_mfma(H->d.act, a, H->adj_img->p, nb, ws.n_cu, s)
-                     : launch_adjoint(prec, mode, a, nb, s);
+  // FP32 and BF16X3 with a network: the sweep on MFMA; otherwise one path
+  // per lane
+  const bool mfma = H && (prec == SL7_F32 || prec == SL7_BF16X3);
+  hipError_t e = mfma ? launch_adjoint_mfma(prec, H->d.act, a,
+                                            (prec == SL7_F32 ? H->adj_img : H->adj_img_x3)->p, nb,
+                                            ws.n_cu, s)
+                      : launch_adjoint(prec, mode, a, nb, s);
   if (e != hipSuccess) return hip_fail(e, "launch adjoint");
   double res[12];
   e = hipMemcpyAsync(res, a.result, sizeof(res), hipMemcpyDeviceToHost, s);

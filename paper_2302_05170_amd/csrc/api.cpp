@@ -282,6 +282,7 @@ void Mlp::drop_device() {
   lane64.reset();
   wth64.reset();
   adj_img.reset();
+  adj_img_x3.reset();
   w0full.reset();
   w0n.reset();
   c0n.reset();

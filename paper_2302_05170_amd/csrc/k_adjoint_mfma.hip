@@ -1,6 +1,8 @@
 // Reverse-mode (adjoint) sweep of the Seven-League online stage with the
-// network on MFMA (FP32 operands, v_mfma_f32_16x16x4_f32): pathwise
-// sensitivities of E[f(Y_T)] to Y0 and theta.
+// network on MFMA: pathwise sensitivities of E[f(Y_T)] to Y0 and theta.
+// Two operand precisions: FP32 (v_mfma_f32_16x16x4_f32) and three-pass
+// split BF16 (v_mfma_f32_16x16x32_bf16 on hi/lo parts of weights and of
+// activations or cotangents, hi*hi + hi*lo + lo*hi in FP32 accumulators).
 //
 // A wave advances 16 paths at a time in the layout of the simulation
 // kernels: paths in the N dimension of 16x16 tiles, lane (g, n) holding
@@ -9,7 +11,8 @@
 //   forward  z_{l+1} = act(W_{l+1} z_l + b_{l+1})     A operand: W packed by rows
 //   reverse  d_l = act'(pre_l) . (W_{l+1}^T d_{l+1})  A operand: W packed by columns
 // so a layer's accumulator tile is directly the B operand of the next
-// product in either direction.  The head's transpose takes the cotangent of
+// product in either direction (in the split mode after its split into
+// hi/lo BF16 halves).  The head's transpose takes the cotangent of
 // the collocation values, ybar_j = lambda L_j(X) (L_j the Lagrange basis at
 // the step's normal), as a 16-row B operand; the first layer, rank one in Y
 // and theta (eq. 6.3/6.4 with the inputs (Y, dt, theta)), reduces the
@@ -44,99 +47,25 @@ __device__ __forceinline__ float u2f(uint32_t x) { return __builtin_bit_cast(flo
 __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f32x4 mfma32(u32x4 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), b, c, 0, 0, 0);
+}
 
-// Bits 4b + r of a 16-unit mask word for the lane's tile of one layer, from
-// the ReLU outputs: bit set iff the output is nonzero (pre-activation > 0).
-// min(bits, 1) is that flag; integer operations only, no condition codes.
-__device__ __forceinline__ uint32_t tile_mask(const f32x4 h[4]) {
+// Bits 4b + r of a 16-unit mask word for the lane's tile of one layer: set
+// iff the pre-activation is > 0, i.e. its bit pattern is a positive integer
+// (+0 and negative values clear the bit, as ReLU'(0) = 0).
+__device__ __forceinline__ uint32_t tile_mask(const f32x4 z[4]) {
   uint32_t w = 0;
 #pragma unroll
   for (int b = 0; b < 4; ++b)
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      w |= __builtin_elementwise_min(f2u(h[b][r]), 1u) << (4 * b + r);
+    for (int r = 0; r < 4; ++r) w |= ((int)f2u(z[b][r]) > 0 ? 1u : 0u) << (4 * b + r);
   return w;
 }
 
 // Logistic function 1 / (1 + e^{-z}), the derivative of Softplus.
 __device__ __forceinline__ float logistic(float z) {
   return fast_rcp(1.f + __builtin_amdgcn_exp2f(-z * 1.44269504088896341f));
-}
-
-// Forward evaluation of the network for NG groups of 16 paths (group s at
-// Y[s]), in the arithmetic of the simulation kernel's FP32 chain (same
-// products in the same order for every path).  A layer's products are
-// issued group after group, so one group's activation and masks can be
-// computed while the other group's products run.  HEAD: also the head
-// tiles (rows 4g..4g+3 of the m outputs).  ReLU: masks of the four hidden
-// layers in m01 / m23.  Softplus with DER (one group): the logistic
-// derivatives of the four pre-activations in der.
-template <int ACT, int NG, bool HEAD, bool DER>
-__device__ __forceinline__ void am_forward(const f32x4* __restrict__ L, int lane,
-                                           const float (&Y)[NG], uint32_t (&m01)[NG],
-                                           uint32_t (&m23)[NG], f32x4 (&y)[NG],
-                                           f32x4 (*der)[4]) {
-  static_assert(!DER || NG == 1, "derivatives for one group");
-  f32x4 z[NG][4], Bv[NG][4];
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const f32x4 w = L[(kAmWy + b) * 64 + lane], c = L[(kAmC0 + b) * 64 + lane];
-#pragma unroll
-    for (int s = 0; s < NG; ++s)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) z[s][b][r] = fmaf(Y[s], w[r], c[r]);
-  }
-  uint32_t mk[NG][4];
-#pragma unroll
-  for (int l = 0; l < 4; ++l) {
-#pragma unroll
-    for (int s = 0; s < NG; ++s) {
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        if constexpr (DER)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) der[l][b][r] = logistic(z[s][b][r]);
-        Bv[s][b] = act4<ACT>(z[s][b]);
-      }
-      if constexpr (ACT == SL7_RELU) mk[s][l] = tile_mask(Bv[s]);
-    }
-    if (l == 3) break;
-#pragma unroll
-    for (int s = 0; s < NG; ++s) {
-      f32x4 acc[4];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[b] = L[(kAmBias + 4 * l + b) * 64 + lane];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        f32x4 A[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) A[b] = L[(kAmFwd + 16 * l + 4 * b + q) * 64 + lane];
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[b] = mfma4(A[b][e], Bv[s][q][e], acc[b]);
-      }
-#pragma unroll
-      for (int b = 0; b < 4; ++b) z[s][b] = acc[b];
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < NG; ++s) {
-    if constexpr (ACT == SL7_RELU) {
-      m01[s] = mk[s][0] | (mk[s][1] << 16);
-      m23[s] = mk[s][2] | (mk[s][3] << 16);
-    }
-    if constexpr (HEAD) {
-      f32x4 t = L[(kAmBias + 12) * 64 + lane];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const f32x4 A = L[(kAmHead + q) * 64 + lane];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) t = mfma4(A[e], Bv[s][q][e], t);
-      }
-      y[s] = t;
-    }
-  }
 }
 
 // Multiplies a cotangent tile by the derivative of layer l's activation.
@@ -159,32 +88,127 @@ __device__ __forceinline__ void am_act_grad(f32x4 d[4], int l, uint32_t m01, uin
     }
 }
 
-// Reverse step through the network for NG groups: from ybar[s] (the head
-// tile's rows) to the cotangent of the first layer's pre-activation, then
-// its reduction against the first-layer weights: dy[s] is the lane's partial
-// sum of d/dY (16 units), th[s][k] that of d/dtheta_k.
-template <int ACT, int NG>
-__device__ __forceinline__ void am_reverse(const f32x4* __restrict__ L, int lane,
-                                           const f32x4 (&ybar)[NG], const uint32_t (&m01)[NG],
-                                           const uint32_t (&m23)[NG], const f32x4 (*der)[4],
-                                           int n_theta, float (&dy)[NG], float (&th)[NG][3]) {
-  f32x4 d[NG][4];
+// First-layer pre-activation z_0 = Y w_Y + c_0 of the lane's 16 units.
+__device__ __forceinline__ void first_layer(const f32x4* __restrict__ L, int lane, int sWy,
+                                            int sC0, float Y, f32x4 z[4]) {
 #pragma unroll
-  for (int s = 0; s < NG; ++s) {
+  for (int b = 0; b < 4; ++b) {
+    const f32x4 w = L[(sWy + b) * 64 + lane], c = L[(sC0 + b) * 64 + lane];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) z[b][r] = fmaf(Y, w[r], c[r]);
+  }
+}
+
+// The cotangent d of the first layer's pre-activation against its weights:
+// returns the lane's partial sum of d/dY (16 units), th[k] that of
+// d/dtheta_k.
+__device__ __forceinline__ float first_layer_vjp(const f32x4* __restrict__ L, int lane, int sWy,
+                                                 int sWth, const f32x4 d[4], int n_theta,
+                                                 float th[3]) {
+  float dy = 0.f;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const f32x4 w = L[(sWy + b) * 64 + lane];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dy = fmaf(d[b][r], w[r], dy);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k < n_theta) {
+      float u = 0.f;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const f32x4 w = L[(sWth + 4 * k + b) * 64 + lane];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) u = fmaf(d[b][r], w[r], u);
+      }
+      th[k] = u;
+    }
+  }
+  return dy;
+}
+
+// ------------------------------------------------------------------------
+// FP32 operands.  K block kb = 4 q + e of a product takes register e of
+// block q of the previous tile.
+// ------------------------------------------------------------------------
+struct AmF32 {
+  static constexpr int kWy = kAmWy, kWth = kAmWth, kC0 = kAmC0, kSlots = kAmSlots;
+
+  // Forward evaluation at Y for the wave's 16 paths, in the arithmetic of
+  // the simulation kernel's FP32 chain (same products in the same order).
+  // HEAD: also the head tile (rows 4g..4g+3 of the m outputs).  ReLU: masks
+  // of the four hidden layers in m01 / m23.  Softplus with DER: the logistic
+  // derivatives of the four pre-activations in der.
+  template <int ACT, bool HEAD, bool DER>
+  static __device__ __forceinline__ f32x4 forward(const f32x4* __restrict__ L, int lane, float Y,
+                                                  uint32_t& m01, uint32_t& m23, f32x4 (*der)[4]) {
+    f32x4 z[4], Bv[4];
+    first_layer(L, lane, kWy, kC0, Y, z);
+    uint32_t mk[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      if constexpr (ACT == SL7_RELU) mk[l] = tile_mask(z);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if constexpr (DER)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) der[l][b][r] = logistic(z[b][r]);
+        Bv[b] = act4<ACT>(z[b]);
+      }
+      if (l == 3) break;
+      f32x4 acc[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[b] = L[(kAmBias + 4 * l + b) * 64 + lane];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        f32x4 A[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) A[b] = L[(kAmFwd + 16 * l + 4 * b + q) * 64 + lane];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[b] = mfma4(A[b][e], Bv[q][e], acc[b]);
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) z[b] = acc[b];
+    }
+    if constexpr (ACT == SL7_RELU) {
+      m01 = mk[0] | (mk[1] << 16);
+      m23 = mk[2] | (mk[3] << 16);
+    }
+    f32x4 y = (f32x4){0.f, 0.f, 0.f, 0.f};
+    if constexpr (HEAD) {
+      y = L[(kAmBias + 12) * 64 + lane];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const f32x4 A = L[(kAmHead + q) * 64 + lane];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) y = mfma4(A[e], Bv[q][e], y);
+      }
+    }
+    return y;
+  }
+
+  // Reverse step through the network: from ybar (the head tile's rows) to
+  // the cotangent of the first layer's pre-activation and its reduction.
+  template <int ACT>
+  static __device__ __forceinline__ float reverse(const f32x4* __restrict__ L, int lane,
+                                                  f32x4 ybar, uint32_t m01, uint32_t m23,
+                                                  const f32x4 (*der)[4], int n_theta,
+                                                  float th[3]) {
+    f32x4 d[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const f32x4 A = L[(kAmRevH + b) * 64 + lane];
       f32x4 acc = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int e = 0; e < 4; ++e) acc = mfma4(A[e], ybar[s][e], acc);
-      d[s][b] = acc;
+      for (int e = 0; e < 4; ++e) acc = mfma4(A[e], ybar[e], acc);
+      d[b] = acc;
     }
-    am_act_grad<ACT>(d[s], 3, m01[s], m23[s], der);
-  }
+    am_act_grad<ACT>(d, 3, m01, m23, der);
 #pragma unroll
-  for (int l = 2; l >= 0; --l) {
-#pragma unroll
-    for (int s = 0; s < NG; ++s) {
+    for (int l = 2; l >= 0; --l) {
       f32x4 acc[4];
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[b] = (f32x4){0.f, 0.f, 0.f, 0.f};
@@ -196,38 +220,114 @@ __device__ __forceinline__ void am_reverse(const f32x4* __restrict__ L, int lane
 #pragma unroll
         for (int e = 0; e < 4; ++e)
 #pragma unroll
-          for (int b = 0; b < 4; ++b) acc[b] = mfma4(A[b][e], d[s][q][e], acc[b]);
+          for (int b = 0; b < 4; ++b) acc[b] = mfma4(A[b][e], d[q][e], acc[b]);
       }
 #pragma unroll
-      for (int b = 0; b < 4; ++b) d[s][b] = acc[b];
-      am_act_grad<ACT>(d[s], l, m01[s], m23[s], der);
+      for (int b = 0; b < 4; ++b) d[b] = acc[b];
+      am_act_grad<ACT>(d, l, m01, m23, der);
     }
+    return first_layer_vjp(L, lane, kWy, kWth, d, n_theta, th);
   }
+};
+
+// ------------------------------------------------------------------------
+// Three-pass split BF16 operands.  A product W x is W_lo x_hi + W_hi x_lo +
+// W_hi x_hi, accumulated in FP32 in that order for every output (the order
+// of the simulation kernel's split chain); x splits as in that kernel
+// (activations) or with its sign (cotangents).
+// ------------------------------------------------------------------------
+struct AmX3 {
+  static constexpr int kWy = kXWy, kWth = kXWth, kC0 = kXC0, kSlots = kXSlots;
+
+  static __device__ __forceinline__ u32x4 w(const f32x4* L, int slot, int lane) {
+    return __builtin_bit_cast(u32x4, L[slot * 64 + lane]);
+  }
+
+  template <int ACT, bool HEAD, bool DER>
+  static __device__ __forceinline__ f32x4 forward(const f32x4* __restrict__ L, int lane, float Y,
+                                                  uint32_t& m01, uint32_t& m23, f32x4 (*der)[4]) {
+    f32x4 z[4];
+    first_layer(L, lane, kWy, kC0, Y, z);
+    uint32_t mk[4];
+    bf16x8 h0, h1, l0, l1;
 #pragma unroll
-  for (int s = 0; s < NG; ++s) {
-    float v = 0.f;
+    for (int l = 0; l < 4; ++l) {
+      if constexpr (ACT == SL7_RELU) mk[l] = tile_mask(z);
+      if constexpr (DER)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) der[l][b][r] = logistic(z[b][r]);
+      if (l == 3 && !HEAD) break;
+      split8<SL7_BF16X3, ACT>(z[0], z[1], h0, l0);
+      split8<SL7_BF16X3, ACT>(z[2], z[3], h1, l1);
+      if (l == 3) break;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int s = 8 * l + 2 * b;
+        f32x4 acc = L[(kXBias + 4 * l + b) * 64 + lane];
+        acc = mfma32(w(L, kXFwdL + s, lane), h0, acc);
+        acc = mfma32(w(L, kXFwdL + s + 1, lane), h1, acc);
+        acc = mfma32(w(L, kXFwdH + s, lane), l0, acc);
+        acc = mfma32(w(L, kXFwdH + s + 1, lane), l1, acc);
+        acc = mfma32(w(L, kXFwdH + s, lane), h0, acc);
+        z[b] = mfma32(w(L, kXFwdH + s + 1, lane), h1, acc);
+      }
+    }
+    if constexpr (ACT == SL7_RELU) {
+      m01 = mk[0] | (mk[1] << 16);
+      m23 = mk[2] | (mk[3] << 16);
+    }
+    f32x4 y = (f32x4){0.f, 0.f, 0.f, 0.f};
+    if constexpr (HEAD) {
+      y = L[(kXBias + 12) * 64 + lane];
+      y = mfma32(w(L, kXFwdL + 24, lane), h0, y);
+      y = mfma32(w(L, kXFwdL + 25, lane), h1, y);
+      y = mfma32(w(L, kXFwdH + 24, lane), l0, y);
+      y = mfma32(w(L, kXFwdH + 25, lane), l1, y);
+      y = mfma32(w(L, kXFwdH + 24, lane), h0, y);
+      y = mfma32(w(L, kXFwdH + 25, lane), h1, y);
+    }
+    return y;
+  }
+
+  template <int ACT>
+  static __device__ __forceinline__ float reverse(const f32x4* __restrict__ L, int lane,
+                                                  f32x4 ybar, uint32_t m01, uint32_t m23,
+                                                  const f32x4 (*der)[4], int n_theta,
+                                                  float th[3]) {
+    f32x4 d[4];
+    bf16x8 h0, h1, l0, l1;
+    // head: the 16 rows of ybar fill the first half of one K block
+    split8_signed_bf16(ybar, (f32x4){0.f, 0.f, 0.f, 0.f}, h0, l0);
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const f32x4 w = L[(kAmWy + b) * 64 + lane];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) v = fmaf(d[s][b][r], w[r], v);
+      f32x4 acc = (f32x4){0.f, 0.f, 0.f, 0.f};
+      acc = mfma32(w(L, kXRevL + 24 + b, lane), h0, acc);
+      acc = mfma32(w(L, kXRevH + 24 + b, lane), l0, acc);
+      d[b] = mfma32(w(L, kXRevH + 24 + b, lane), h0, acc);
     }
-    dy[s] = v;
+    am_act_grad<ACT>(d, 3, m01, m23, der);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      if (k < n_theta) {
-        float u = 0.f;
+    for (int l = 2; l >= 0; --l) {
+      split8_signed_bf16(d[0], d[1], h0, l0);
+      split8_signed_bf16(d[2], d[3], h1, l1);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const f32x4 w = L[(kAmWth + 4 * k + b) * 64 + lane];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) u = fmaf(d[s][b][r], w[r], u);
-        }
-        th[s][k] = u;
+      for (int b = 0; b < 4; ++b) {
+        const int s = 8 * l + 2 * b;
+        f32x4 acc = (f32x4){0.f, 0.f, 0.f, 0.f};
+        acc = mfma32(w(L, kXRevL + s, lane), h0, acc);
+        acc = mfma32(w(L, kXRevL + s + 1, lane), h1, acc);
+        acc = mfma32(w(L, kXRevH + s, lane), l0, acc);
+        acc = mfma32(w(L, kXRevH + s + 1, lane), l1, acc);
+        acc = mfma32(w(L, kXRevH + s, lane), h0, acc);
+        d[b] = mfma32(w(L, kXRevH + s + 1, lane), h1, acc);
       }
+      am_act_grad<ACT>(d, l, m01, m23, der);
     }
+    return first_layer_vjp(L, lane, kWy, kWth, d, n_theta, th);
   }
-}
+};
 
 // Sum over the path's four lanes, in the same order on each of them.
 __device__ __forceinline__ float path_sum(float v) {
@@ -239,7 +339,7 @@ __device__ __forceinline__ double path_sum(double v) {
   return v + __shfl_xor(v, 32);
 }
 
-// The step normals of the lane's path, drawn as in the simulation kernel:
+// The step normals of the lane's path, drawn as in the simulation kernels:
 // for the 16-step block containing step i, lane group g draws the Philox
 // quad 4 (i / 16) + g (steps 16 (i / 16) + 4 g .. + 3), and X_i is read from
 // the lane of the path in group (i / 4) % 4.  The block is kept, so a run of
@@ -259,31 +359,25 @@ struct StepNormals {
   }
 };
 
-// One forward step of NG groups (Y[s] -> Y_{i+1}); with STORE each group's
-// evaluation state goes to its lane slot st[s]: ReLU masks of layers 0-1
-// and 2-3 (bit 16 (l % 2) + 4 b + r), Y_i, the clamp flag.
-template <int ACT, int NG, bool STORE>
-__device__ __forceinline__ void am_step(const f32x4* L, int lane, float (&Y)[NG],
-                                        const float (&X)[NG], const float xr[4],
-                                        const float lr[4], bool clamp, u32x4* const* st) {
-  uint32_t m01[NG], m23[NG];
-  f32x4 y[NG];
-#pragma unroll
-  for (int s = 0; s < NG; ++s) m01[s] = m23[s] = 0u;
-  am_forward<ACT, NG, true, false>(L, lane, Y, m01, m23, y, nullptr);
-#pragma unroll
-  for (int s = 0; s < NG; ++s) {
-    float Yn = interp_rows(X[s], y[s], xr, lr);
-    const bool cl = clamp && Yn < 0.f;
-    if (cl) Yn = 0.f;
-    if constexpr (STORE) *st[s] = (u32x4){m01[s], m23[s], f2u(Y[s]), cl ? 1u : 0u};
-    Y[s] = Yn;
-  }
+// One forward step of the group (Y -> Y_{i+1}); with STORE the step's
+// evaluation state goes to the lane's segment-buffer slot st: ReLU masks of
+// layers 0-1 and 2-3 (bit 16 (l % 2) + 4 b + r), Y_i, the clamp flag.
+template <class Net, int ACT, bool STORE>
+__device__ __forceinline__ float am_step(const f32x4* L, int lane, float Y, float X,
+                                         const float xr[4], const float lr[4], bool clamp,
+                                         u32x4* st) {
+  uint32_t m01 = 0, m23 = 0;
+  const f32x4 y = Net::template forward<ACT, true, false>(L, lane, Y, m01, m23, nullptr);
+  float Yn = interp_rows(X, y, xr, lr);
+  const bool cl = clamp && Yn < 0.f;
+  if (cl) Yn = 0.f;
+  if constexpr (STORE) *st = (u32x4){m01, m23, f2u(Y), cl ? 1u : 0u};
+  return Yn;
 }
 
-// The sweep for one 64-path block, NG groups of 16 paths at a time (groups
-// t .. t + NG - 1).  Lane (g, n) ends with the results of path 16 g + n.
-template <int ACT, int NG>
+// The sweep for one 64-path block, 16 paths (group t) at a time.  Lane
+// (g, n) ends with the results of path 16 g + n in q.
+template <class Net, int ACT>
 __device__ __forceinline__ void am_block(const AdjArgs& a, const InstDev& I, const f32x4* L,
                                          int64_t blk, const float xr[4], const float lr[4],
                                          int lane, int g, int n, double (&q)[6]) {
@@ -293,142 +387,95 @@ __device__ __forceinline__ void am_block(const AdjArgs& a, const InstDev& I, con
   const bool clamp = I.clamp_zero != 0;
   const float K = I.K_f;
   float* ck = (float*)a.ckpt_buf;
-  // segment state: [block][group slot][step][lane], k steps per group slot
-  u32x4* const st0 = (u32x4*)a.state_buf + blk * (int64_t)(2 * k) * 64 + lane;
-  for (int t = 0; t < 4; t += NG) {
+  // segment state of the block: [step][lane]
+  u32x4* const st = (u32x4*)a.state_buf + blk * (int64_t)k * 64 + lane;
+  for (int t = 0; t < 4; ++t) {
     if (blk * 64 + 16 * t >= N) break;
-    int64_t p[NG], gp[NG];
-    bool valid[NG];
-    u32x4* st[NG];
-    StepNormals nrm[NG];
-#pragma unroll
-    for (int s = 0; s < NG; ++s) {
-      p[s] = blk * 64 + 16 * (t + s) + n;
-      valid[s] = p[s] < N;
-      gp[s] = I.path_offset + p[s];
-      st[s] = st0 + s * k * 64;
-    }
-    // forward pass: checkpoints (every lane of a path writes, and later reads
-    // back, the same value), and the last segment's state
-    float Y[NG], X[NG];
-#pragma unroll
-    for (int s = 0; s < NG; ++s) Y[s] = I.Y0_f;
+    const int64_t p = blk * 64 + 16 * t + n;
+    const bool valid = p < N;
+    const int64_t gp = I.path_offset + p;
+    StepNormals nrm;
+    // forward pass: checkpoints (every lane of a path writes, and later
+    // reads back, the same value), and the last segment's state
+    float Y = I.Y0_f;
     for (int i = 0; i < M; ++i) {
-#pragma unroll
-      for (int s = 0; s < NG; ++s) {
-        if (i % k == 0 && valid[s]) ck[(int64_t)(i / k) * N + p[s]] = Y[s];
-        X[s] = nrm[s].get(a, i, gp[s], tag, g, n);
-      }
-      if (i >= ib_last) {
-        u32x4* sl[NG];
-#pragma unroll
-        for (int s = 0; s < NG; ++s) sl[s] = st[s] + (i - ib_last) * 64;
-        am_step<ACT, NG, true>(L, lane, Y, X, xr, lr, clamp, sl);
-      } else {
-        am_step<ACT, NG, false>(L, lane, Y, X, xr, lr, clamp, nullptr);
-      }
+      if (i % k == 0 && valid) ck[(int64_t)(i / k) * N + p] = Y;
+      const float X = nrm.get(a, i, gp, tag, g, n);
+      if (i >= ib_last)
+        Y = am_step<Net, ACT, true>(L, lane, Y, X, xr, lr, clamp, st + (i - ib_last) * 64);
+      else
+        Y = am_step<Net, ACT, false>(L, lane, Y, X, xr, lr, clamp, nullptr);
     }
-    double f[NG], thb[NG][3];
-    float lam[NG];
-#pragma unroll
-    for (int s = 0; s < NG; ++s) {
-      f[s] = a.payoff == 0 ? (double)Y[s] : fmax((double)Y[s] - (double)K, 0.0);
-      lam[s] = a.payoff == 0 ? 1.f : (Y[s] > K ? 1.f : 0.f);
-      thb[s][0] = thb[s][1] = thb[s][2] = 0.0;
-    }
+    const double f = a.payoff == 0 ? (double)Y : fmax((double)Y - (double)K, 0.0);
+    float lam = a.payoff == 0 ? 1.f : (Y > K ? 1.f : 0.f);
+    double thb[3] = {0.0, 0.0, 0.0};
     for (int seg = nseg - 1; seg >= 0; --seg) {
       const int ib = seg * k, ie = min(ib + k, M);
       if (seg != nseg - 1) {
-        float Yc[NG];
-#pragma unroll
-        for (int s = 0; s < NG; ++s) Yc[s] = valid[s] ? ck[(int64_t)seg * N + p[s]] : I.Y0_f;
-        for (int i = ib; i < ie; ++i) {
-#pragma unroll
-          for (int s = 0; s < NG; ++s) X[s] = nrm[s].get(a, i, gp[s], tag, g, n);
-          u32x4* sl[NG];
-#pragma unroll
-          for (int s = 0; s < NG; ++s) sl[s] = st[s] + (i - ib) * 64;
-          am_step<ACT, NG, true>(L, lane, Yc, X, xr, lr, clamp, sl);
-        }
+        float Yc = valid ? ck[(int64_t)seg * N + p] : I.Y0_f;
+        for (int i = ib; i < ie; ++i)
+          Yc = am_step<Net, ACT, true>(L, lane, Yc, nrm.get(a, i, gp, tag, g, n), xr, lr, clamp,
+                                       st + (i - ib) * 64);
       }
       for (int i = ie - 1; i >= ib; --i) {
-        f32x4 ybar[NG];
-        uint32_t m01[NG], m23[NG];
-        float Yi[NG];
+        const u32x4 sv = st[(i - ib) * 64];
+        const float X = nrm.get(a, i, gp, tag, g, n);
+        // Lagrange basis at X over the lane's rows, as the forward
+        // interpolation forms it
+        f32x4 tr;
+        float den = 0.f;
 #pragma unroll
-        for (int s = 0; s < NG; ++s) {
-          const u32x4 sv = st[s][(i - ib) * 64];
-          m01[s] = sv[0];
-          m23[s] = sv[1];
-          Yi[s] = u2f(sv[2]);
-          const float Xs = nrm[s].get(a, i, gp[s], tag, g, n);
-          // Lagrange basis at X over the lane's rows, as the forward
-          // interpolation forms it
-          f32x4 tr;
-          float den = 0.f;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            float dx = Xs - xr[r];
-            dx = dx == 0.f ? 1e-30f : dx;
-            tr[r] = lr[r] * fast_rcp(dx);
-            den += tr[r];
-          }
-          den = path_sum(den);
-          const float sc = sv[3] == 0u ? lam[s] * fast_rcp(den) : 0.f;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) ybar[s][r] = tr[r] * sc;
+        for (int r = 0; r < 4; ++r) {
+          float dx = X - xr[r];
+          dx = dx == 0.f ? 1e-30f : dx;
+          tr[r] = lr[r] * fast_rcp(dx);
+          den += tr[r];
         }
-        float dy[NG], th[NG][3];
+        den = path_sum(den);
+        const float sc = sv[3] == 0u ? lam * fast_rcp(den) : 0.f;
+        f32x4 ybar;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ybar[r] = tr[r] * sc;
+        float th[3] = {0.f, 0.f, 0.f};
+        float dy;
         if constexpr (ACT == SL7_RELU) {
-          am_reverse<ACT, NG>(L, lane, ybar, m01, m23, nullptr, a.n_theta, dy, th);
+          dy = Net::template reverse<ACT>(L, lane, ybar, sv[0], sv[1], nullptr, a.n_theta, th);
         } else {
-          static_assert(NG == 1, "Softplus: one group");
-          f32x4 der[4][4], yd[NG];
-          uint32_t u0[NG], u1[NG];
-          am_forward<ACT, NG, false, true>(L, lane, Yi, u0, u1, yd, der);
-          am_reverse<ACT, NG>(L, lane, ybar, u0, u1, der, a.n_theta, dy, th);
+          f32x4 der[4][4];
+          uint32_t u0, u1;
+          Net::template forward<ACT, false, true>(L, lane, u2f(sv[2]), u0, u1, der);
+          dy = Net::template reverse<ACT>(L, lane, ybar, 0u, 0u, der, a.n_theta, th);
         }
+        lam = path_sum(dy);
+        // the lane's share of the theta-cotangent; the path's four lanes
+        // are summed once, after the sweep
 #pragma unroll
-        for (int s = 0; s < NG; ++s) {
-          lam[s] = path_sum(dy[s]);
-          // the lane's share of the theta-cotangent; the path's four lanes
-          // are summed once, after the sweep
-#pragma unroll
-          for (int kk = 0; kk < 3; ++kk)
-            if (kk < a.n_theta) thb[s][kk] += (double)th[s][kk];
-        }
+        for (int kk = 0; kk < 3; ++kk)
+          if (kk < a.n_theta) thb[kk] += (double)th[kk];
       }
     }
 #pragma unroll
-    for (int s = 0; s < NG; ++s) {
-#pragma unroll
-      for (int kk = 0; kk < 3; ++kk) thb[s][kk] = path_sum(thb[s][kk]);
-      if (g == t + s) {
-        q[0] = f[s];
-        q[1] = (double)lam[s];
-        q[2] = thb[s][0];
-        q[3] = thb[s][1];
-        q[4] = thb[s][2];
-      }
+    for (int kk = 0; kk < 3; ++kk) thb[kk] = path_sum(thb[kk]);
+    if (g == t) {
+      q[0] = f;
+      q[1] = (double)lam;
+      q[2] = thb[0];
+      q[3] = thb[1];
+      q[4] = thb[2];
     }
   }
 }
 
-// Groups per wave.  One: two groups per wave need one wave per SIMD (the
-// second group's registers), which measured slower than two waves of one
-// group each (44.3 against 40.1 ms for 2^22 paths x 16 steps).
-template <int ACT>
-constexpr int am_groups() { return 1; }
-
-template <int ACT, int WAVES>
+template <class Net, int ACT, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_adjoint_mfma(AdjArgs a, const u32x4* __restrict__ img,
                                                              int64_t n_blocks) {
-  __shared__ f32x4 L[kAmSlots * 64];
+  __shared__ f32x4 L[Net::kSlots * 64];
   const InstDev& I = a.inst[0];
-  for (int i = threadIdx.x; i < kAmC0 * 64; i += blockDim.x) L[i] = __builtin_bit_cast(f32x4, img[i]);
+  for (int i = threadIdx.x; i < Net::kC0 * 64; i += blockDim.x)
+    L[i] = __builtin_bit_cast(f32x4, img[i]);
   for (int i = threadIdx.x; i < 4 * 64; i += blockDim.x) {
     const int b = i >> 6, g = (i & 63) >> 4;
-    L[kAmC0 * 64 + i] = *(const f32x4*)(I.c0 + 16 * b + 4 * g);
+    L[Net::kC0 * 64 + i] = *(const f32x4*)(I.c0 + 16 * b + 4 * g);
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
@@ -439,7 +486,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_adjoint_mfma(AdjArgs a, const u3
   for (int64_t blk = (int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6); blk < n_blocks;
        blk += wstride) {
     double q[6] = {0, 0, 0, 0, 0, 0};
-    am_block<ACT, am_groups<ACT>()>(a, I, L, blk, xr, lr, lane, g, n, q);
+    am_block<Net, ACT>(a, I, L, blk, xr, lr, lane, g, n, q);
     // lane l now holds path l of the block
     const int64_t p = blk * 64 + lane;
     const bool valid = p < N;
@@ -472,28 +519,31 @@ __global__ __launch_bounds__(64 * WAVES) void k_adjoint_mfma(AdjArgs a, const u3
   }
 }
 
-// Waves per workgroup: the LDS image allows one workgroup per CU; ReLU keeps
-// few registers per lane (four waves per SIMD), Softplus holds the logistic
-// derivatives of a step (two).
-template <int ACT>
-constexpr int am_waves() { return 8; }
+// Eight waves per workgroup: the LDS image allows one workgroup per CU, and
+// two waves per SIMD measured fastest (one wave with two 16-path groups:
+// 44.3 against 40.1 ms in FP32 for 2^22 paths x 16 steps; three waves spill).
+constexpr int kAmWaves = 8;
 
-template <int ACT>
-static hipError_t launch_act(const AdjArgs& a, const void* img, int64_t n_blocks, int n_cu,
+template <class Net, int ACT>
+static hipError_t launch_net(const AdjArgs& a, const void* img, int64_t n_blocks, int n_cu,
                              hipStream_t s) {
-  constexpr int W = am_waves<ACT>();
-  const int64_t wgs = (n_blocks + W - 1) / W;
+  const int64_t wgs = (n_blocks + kAmWaves - 1) / kAmWaves;
   const int grid = (int)(wgs < n_cu ? wgs : n_cu);
-  hipLaunchKernelGGL((k_adjoint_mfma<ACT, W>), dim3(grid), dim3(64 * W), 0, s, a,
-                     (const u32x4*)img, n_blocks);
+  hipLaunchKernelGGL((k_adjoint_mfma<Net, ACT, kAmWaves>), dim3(grid), dim3(64 * kAmWaves), 0, s,
+                     a, (const u32x4*)img, n_blocks);
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_mfma(int act, const AdjArgs& a, const void* img, int64_t n_blocks,
-                               int n_cu, hipStream_t s) {
+hipError_t launch_adjoint_mfma(int prec, int act, const AdjArgs& a, const void* img,
+                               int64_t n_blocks, int n_cu, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
-  const hipError_t e = act == SL7_RELU ? launch_act<SL7_RELU>(a, img, n_blocks, n_cu, s)
-                                       : launch_act<SL7_SOFTPLUS>(a, img, n_blocks, n_cu, s);
+  hipError_t e;
+  if (prec == SL7_BF16X3)
+    e = act == SL7_RELU ? launch_net<AmX3, SL7_RELU>(a, img, n_blocks, n_cu, s)
+                        : launch_net<AmX3, SL7_SOFTPLUS>(a, img, n_blocks, n_cu, s);
+  else
+    e = act == SL7_RELU ? launch_net<AmF32, SL7_RELU>(a, img, n_blocks, n_cu, s)
+                        : launch_net<AmF32, SL7_SOFTPLUS>(a, img, n_blocks, n_cu, s);
   if (e != hipSuccess) return e;
   return launch_adjoint_finalize(a, n_blocks, s);
 }

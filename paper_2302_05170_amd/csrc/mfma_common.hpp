@@ -1,6 +1,7 @@
 // Helpers shared by the MFMA kernels (simulation and adjoint sweep):
-// activations on FP32 values and the barycentric interpolation over the
-// rows a lane holds of a 16x16 head tile.
+// activations on FP32 values, the barycentric interpolation over the rows a
+// lane holds of a 16x16 head tile, and the 16-bit operand types with the
+// three-pass split of FP32 values into them.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -97,6 +98,150 @@ __device__ __forceinline__ void lane_rows(const Args& a, int m, int g, float xr[
         lr[r] = a.ls[j];
       }
   }
+}
+
+// ------------------------------------------------------------------------
+// BF16 / FP16 operands (v_mfma_f32_16x16x32_{bf16,f16}).
+// ------------------------------------------------------------------------
+template <int P>
+struct H16;
+
+template <>
+struct H16<SL7_BF16> {
+  typedef bf16x8 v8;
+  typedef __bf16 elem;
+  static __device__ __forceinline__ f32x4 mfma(v8 a, v8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  // RNE conversion of two floats, then ReLU on the packed halves: a negative
+  // value has its sign bit set, so a signed 16-bit max with 0 clears it.
+  static __device__ __forceinline__ uint32_t pack_relu(float x, float y) {
+    const bf16x2 h = __builtin_convertvector((f32x2){x, y}, bf16x2);
+    const s16x2 s = __builtin_elementwise_max(__builtin_bit_cast(s16x2, h), (s16x2){0, 0});
+    return __builtin_bit_cast(uint32_t, s);
+  }
+};
+
+template <>
+struct H16<SL7_F16> {
+  typedef f16x8 v8;
+  typedef _Float16 elem;
+  static __device__ __forceinline__ f32x4 mfma(v8 a, v8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ uint32_t pack_relu(float x, float y) {
+    const f16x2 h = __builtin_convertvector((f32x2){x, y}, f16x2);
+    const s16x2 s = __builtin_elementwise_max(__builtin_bit_cast(s16x2, h), (s16x2){0, 0});
+    return __builtin_bit_cast(uint32_t, s);
+  }
+};
+
+// ------------------------------------------------------------------------
+// Three-pass split operands: x = hi + lo with hi = rn(x) and lo = rn(x - hi)
+// in the 16-bit type, for weights and activations; each product is
+// hi*hi + hi*lo + lo*hi accumulated in FP32 (the lo*lo term, ~2^-16 of the
+// product for BF16, is dropped).  Removes the rounding bias of one-pass
+// 16-bit operands at three times the MFMA work.
+// ------------------------------------------------------------------------
+template <int P>
+struct Split16;
+
+template <>
+struct Split16<SL7_BF16X3> {
+  typedef bf16x8 v8;
+  typedef bf16x2 v2;
+  static constexpr int base = SL7_BF16;
+};
+
+template <>
+struct Split16<SL7_F16X3> {
+  typedef f16x8 v8;
+  typedef f16x2 v2;
+  static constexpr int base = SL7_F16;
+};
+
+// x - f32(h), h the FP16 value in the low / high half of hw: one
+// v_fma_mix_f32 (-h * 1 + x, h converted exactly inside the instruction).
+// (The result takes x's register.)
+__device__ __forceinline__ float minus_f16_lo(float x, uint32_t hw) {
+  asm("v_fma_mix_f32 %0, -%1, 1.0, %0 op_sel_hi:[1,0,0]" : "+v"(x) : "v"(hw));
+  return x;
+}
+__device__ __forceinline__ float minus_f16_hi(float x, uint32_t hw) {
+  asm("v_fma_mix_f32 %0, -%1, 1.0, %0 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(x) : "v"(hw));
+  return x;
+}
+
+// The (hi, lo) pair of B operands for eight activations, ReLU applied.
+// BF16: hi is the activation truncated to its upper 16 bits and lo = x - hi
+// (exact in FP32, then rounded to BF16); hi and lo carry the sign of x, so
+// ReLU is a signed 16-bit max of the packed halves.  FP16: hi rounded toward
+// zero, lo = x - hi rounded to nearest, ReLU the same way.
+template <int P, int ACT>
+__device__ __forceinline__ void split8(f32x4 a, f32x4 b, typename Split16<P>::v8& hi,
+                                       typename Split16<P>::v8& lo) {
+  typedef typename Split16<P>::v2 v2;
+  float v[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+  if constexpr (ACT != SL7_RELU) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = softplus_f(v[i]);  // >= 0: the ReLU below is a no-op
+  }
+  u32x4 wh, wl;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if constexpr (P == SL7_BF16X3) {
+      const uint32_t u0 = __builtin_bit_cast(uint32_t, v[2 * q]);
+      const uint32_t u1 = __builtin_bit_cast(uint32_t, v[2 * q + 1]);
+      // upper halves of u0 (low result half) and u1 (high result half)
+      const uint32_t h = __builtin_amdgcn_perm(u1, u0, 0x07060302u);
+      // x - hi, exact in FP32 (hi is x with its low 16 bits cleared).  A
+      // BF16 dot product against (-1, 0) does the same in one instruction
+      // per value but issues at a lower rate: measured slower here.
+      const float l0 = v[2 * q] - __builtin_bit_cast(float, u0 & 0xffff0000u);
+      const float l1 = v[2 * q + 1] - __builtin_bit_cast(float, u1 & 0xffff0000u);
+      const v2 l = __builtin_convertvector((f32x2){l0, l1}, v2);
+      const s16x2 hs = __builtin_elementwise_max(__builtin_bit_cast(s16x2, h), (s16x2){0, 0});
+      const s16x2 ls = __builtin_elementwise_max(__builtin_bit_cast(s16x2, l), (s16x2){0, 0});
+      wh[q] = __builtin_bit_cast(uint32_t, hs);
+      wl[q] = __builtin_bit_cast(uint32_t, ls);
+    } else {
+      // hi: both values rounded toward zero to FP16 in one instruction, then
+      // ReLU on the packed halves (a negative x gives hi = 0).  lo = x - hi,
+      // exact in FP32, one mixed-precision FMA per value reading hi's half
+      // in place; it has the sign of x (hi was truncated), so the ReLU on
+      // the packed lo clears it exactly when x < 0.
+      const float x0 = v[2 * q], x1 = v[2 * q + 1];
+      const s16x2 hs = __builtin_elementwise_max(
+          __builtin_bit_cast(s16x2, __builtin_amdgcn_cvt_pkrtz(x0, x1)), (s16x2){0, 0});
+      const uint32_t hu = __builtin_bit_cast(uint32_t, hs);
+      const float l0 = minus_f16_lo(x0, hu), l1 = minus_f16_hi(x1, hu);
+      const s16x2 ls = __builtin_elementwise_max(
+          __builtin_bit_cast(s16x2, __builtin_convertvector((f32x2){l0, l1}, v2)), (s16x2){0, 0});
+      wh[q] = hu;
+      wl[q] = __builtin_bit_cast(uint32_t, ls);
+    }
+  }
+  hi = __builtin_bit_cast(typename Split16<P>::v8, wh);
+  lo = __builtin_bit_cast(typename Split16<P>::v8, wl);
+}
+
+// The (hi, lo) pair of BF16 B operands for eight values of either sign: hi
+// the value truncated to its upper 16 bits, lo = x - hi (exact in FP32)
+// rounded to nearest.  For cotangents, which no activation touches.
+__device__ __forceinline__ void split8_signed_bf16(f32x4 a, f32x4 b, bf16x8& hi, bf16x8& lo) {
+  const float v[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+  u32x4 wh, wl;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t u0 = __builtin_bit_cast(uint32_t, v[2 * q]);
+    const uint32_t u1 = __builtin_bit_cast(uint32_t, v[2 * q + 1]);
+    wh[q] = __builtin_amdgcn_perm(u1, u0, 0x07060302u);
+    const float l0 = v[2 * q] - __builtin_bit_cast(float, u0 & 0xffff0000u);
+    const float l1 = v[2 * q + 1] - __builtin_bit_cast(float, u1 & 0xffff0000u);
+    wl[q] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){l0, l1}, bf16x2));
+  }
+  hi = __builtin_bit_cast(bf16x8, wh);
+  lo = __builtin_bit_cast(bf16x8, wl);
 }
 
 }  // namespace sl7

@@ -38,10 +38,12 @@ hipError_t launch_adjoint(int prec, int mode, const AdjArgs& a, int64_t n_blocks
 // Means and standard errors of the block partials into a.result.
 hipError_t launch_adjoint_finalize(const AdjArgs& a, int64_t n_blocks, hipStream_t s);
 
-// The sweep with the network on MFMA (FP32 operands), ReLU or Softplus;
-// img: the LDS image below (kAmC0 slots), n_cu: compute units.
-hipError_t launch_adjoint_mfma(int act, const AdjArgs& a, const void* img, int64_t n_blocks,
-                               int n_cu, hipStream_t s);
+// The sweep with the network on MFMA, prec SL7_F32 (FP32 operands) or
+// SL7_BF16X3 (three-pass split BF16 operands), ReLU or Softplus; img: the
+// LDS image of that precision below (its host-filled slots), n_cu: compute
+// units.
+hipError_t launch_adjoint_mfma(int prec, int act, const AdjArgs& a, const void* img,
+                               int64_t n_blocks, int n_cu, hipStream_t s);
 
 // Slots of the MFMA sweep's LDS image (one 16-byte slot per lane, 64 lanes
 // per slot).  The host fills slots [0, kAmC0); the kernel fills the
@@ -58,5 +60,18 @@ hipError_t launch_adjoint_mfma(int act, const AdjArgs& a, const void* img, int64
 constexpr int kAmFwd = 0, kAmHead = 48, kAmBias = 52, kAmWy = 65, kAmRev = 69, kAmRevH = 117,
               kAmWth = 121, kAmC0 = 133, kAmSlots = 137;
 static_assert(kAmWy + 4 == kAmRev && kAmWth + 12 == kAmC0, "slot map");
+
+// The BF16X3 image: 16-byte slots of eight BF16 values (weights, as hi =
+// rn(w) and lo = rn(w - hi) in two copies of each layout) or four floats.
+// Element e of K block c stands for unit f(c, g, e) = 16 (2 c + e / 4) +
+// 4 g + e % 4 of a layer (the order of the 16-bit B operands).
+//   kXFwd[h|l] + 8 l + 2 b + c : W_{l+1}[16 b + i][f(c, g, e)]
+//   kXFwd[h|l] + 24 + c        : W_head[i][f(c, g, e)]              (i < m)
+//   kXRev[h|l] + 8 l + 2 b + c : W_{l+1}[f(c, g, e)][16 b + i]
+//   kXRev[h|l] + 24 + b        : W_head[f(0, g, e)][16 b + i]       (f < m)
+//   kXBias, kXWy, kXWth, kXC0  : as kAmBias, kAmWy, kAmWth, kAmC0 (FP32)
+constexpr int kXFwdH = 0, kXFwdL = 26, kXRevH = 52, kXRevL = 80, kXBias = 108, kXWy = 121,
+              kXWth = 125, kXC0 = 137, kXSlots = 141;
+static_assert(kXFwdL + 26 == kXRevH && kXRevL + 28 == kXBias && kXWth + 12 == kXC0, "slot map");
 
 }  // namespace sl7

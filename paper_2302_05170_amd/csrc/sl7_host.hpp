@@ -114,7 +114,7 @@ struct Mlp {
   // one-path-per-lane layouts (net_lane.hpp) in FP64 / FP32 and the theta
   // weights of the first layer (FP64) for the lane kernels and the adjoint
   std::unique_ptr<DevBuf> lane64, wth64;  // FP64 lane layout of the adjoint sweep
-  std::unique_ptr<DevBuf> adj_img;        // LDS image of the FP32 MFMA adjoint sweep
+  std::unique_ptr<DevBuf> adj_img, adj_img_x3;  // LDS images of the MFMA adjoint sweep
   // compiled piecewise-linear forms by instance (model, dt, theta); cleared
   // with the device copies whenever the parameters change
   std::map<std::array<double, 5>, std::shared_ptr<PwlPieces>> pwl_cache;

@@ -152,11 +152,12 @@ def test_checkpoint_interval_does_not_change_results(S, H):
 def test_adjoint_vs_central_differences_with_crn(S, H):
     """The adjoint workload: N = 2^22, M = 16, K = 1, checkpoint every 4; bumps 1e-4 on Y0,
     sigma and mu; FP64 differences; gate 1e-3 relative for the FP64 sweep and
-    for the FP32 sweep on MFMA."""
+    for the FP32 and BF16X3 sweeps on MFMA."""
     c = W.CONFIGS["gbm_adjoint_2p22x16"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], c["M"], c["m"], c["N"], K=c["K"])
     g = S.adjoint(pr, H, prec="f64", seed=c["seed"], payoff=1, ckpt_every=c["ckpt"])
     g32 = S.adjoint(pr, H, prec="f32", seed=c["seed"], payoff=1, ckpt_every=c["ckpt"])
+    gx3 = S.adjoint(pr, H, prec="bf16x3", seed=c["seed"], payoff=1, ckpt_every=c["ckpt"])
     h = 1e-4
     for q in range(3):
         def bumped(d):
@@ -170,10 +171,11 @@ def test_adjoint_vs_central_differences_with_crn(S, H):
             st, _ = S.simulate(p2, H, prec="f64", seed=c["seed"])
             return st["mean"][1]
         fd = (bumped(h) - bumped(-h)) / (2 * h)
-        print(f"param {q}: adjoint {g['grad'][q]:.8f} (FP32 MFMA {g32['grad'][q]:.8f}) "
-              f"fd {fd:.8f}")
+        print(f"param {q}: adjoint {g['grad'][q]:.8f} (FP32 MFMA {g32['grad'][q]:.8f}, "
+              f"BF16X3 MFMA {gx3['grad'][q]:.8f}) fd {fd:.8f}")
         assert abs(g["grad"][q] - fd) <= 1e-3 * abs(fd)
         assert abs(g32["grad"][q] - fd) <= 1e-3 * abs(fd)
+        assert abs(gx3["grad"][q] - fd) <= 1e-3 * abs(fd)
 
 
 def test_analytic_map_greeks_vs_black_scholes(S):
