@@ -359,11 +359,24 @@ def main():
             for n in P["path_counts"]:
                 pro = S.Problem(P["model"], P["theta"], P["Y0"], P["T"], P["M"], P["m"], n, K=P["K"])
                 wall_o, _, st_o = time_calls(S, pro, Hou, prec, P["seed"], 20, 2, stats=True)
+                # the same call as one captured graph, replayed (sl7_simulate_batched
+                # with one instance): the per-call host work of a small shape
+                for _ in range(2):
+                    S.simulate_batched([pro], Hou, prec=prec, seed=P["seed"], use_graph=True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(20):
+                    st_g = S.simulate_batched([pro], Hou, prec=prec, seed=P["seed"],
+                                              use_graph=True)[0]
+                wall_g = (time.perf_counter() - t0) / 20
                 ou.setdefault(prec, {})[str(n)] = {
                     "ms_per_run": wall_o * 1e3, "path_steps_per_s": n * P["M"] / wall_o,
+                    "ms_per_run_graph_replay": wall_g * 1e3,
+                    "graph_replay_equals_call": st_g["mean"] == st_o["mean"],
                     "mean_YT": st_o["mean"][0], "paper_mx150_s": PAPER_T61_PARALLEL_S[n]}
             log(f"OU 4x50 softplus {prec}: " + ", ".join(
-                f"N={k} {v['ms_per_run']:.3f} ms" for k, v in ou[prec].items()))
+                f"N={k} {v['ms_per_run']:.3f} ms ({v['ms_per_run_graph_replay']:.3f} ms replayed)"
+                for k, v in ou[prec].items()))
         # the paper's 7L-CDC column of Table 6.1: the same shapes through the CDC variant
         for prec in ("f32", "f64"):
             for n in P["path_counts"]:

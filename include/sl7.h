@@ -88,6 +88,9 @@ extern "C" {
  * piece, found through a uniform grid over the breakpoints; lane arithmetic
  * (piece search, y_j, interpolation, update) in FP32 or FP64.  Mathematically
  * identical to evaluating the network, to rounding. */
+/* Precision codes are plain int arguments (named `prec`): an int has the
+ * same size and passing convention under every C and C++ compiler, which a
+ * C enum type does not guarantee across a shared-library boundary. */
 #define SL7_F64 0
 #define SL7_F32 1
 #define SL7_BF16 2
@@ -338,7 +341,13 @@ int sl7_train(sl7_mlp* H, const sl7_train_spec* spec, const float* X_dev,
 
 /* Gradient of the loss over the B rows (one minibatch) with respect to the
  * parameter vector (same layout as the parameters) into grad_dev (FP32,
- * device); loss_host: NULL or the loss.  Synchronises `stream`. */
+ * device); loss_host: NULL or the loss.  Synchronises `stream`.
+ * This is the training step's weight gradient as its own call: with
+ * sl7_train (whole epochs, Adam in place) it replaces a single-step train
+ * call, leaving the optimiser of a single step to the caller (the Python
+ * binding's SL7TrainLoss feeds it to torch.autograd).  The same weight
+ * gradient is why sl7_adjoint has no weight-gradient output: the network's
+ * parameters enter training through this loss, not through E[f(Y_T)]. */
 int sl7_train_grad(const sl7_mlp* H, const float* X_dev, const float* Y_dev, int64_t B,
                    float* grad_dev, double* loss_host, void* stream);
 
