@@ -20,9 +20,9 @@
 //
 // Sweep per 16-path group (Algorithm I, steps 3-6, then backwards): the
 // forward pass stores Y every `ckpt` steps and, for the steps of the last
-// segment, the evaluation state (ReLU masks, the state Y_i for Softplus,
-// the clamp flag); each earlier segment is recomputed from its checkpoint
-// with the same Philox counters before its reverse steps.  Softplus
+// two segments, the evaluation state (ReLU masks, the state Y_i for
+// Softplus, the clamp flag); each earlier segment is recomputed from its
+// checkpoint with the same Philox counters before its reverse steps.  Softplus
 // recomputes the pre-activations of a step from Y_i in its reverse step for
 // the logistic derivative.  lambda = dY_T/dY_i runs backwards in FP32; the
 // theta-cotangent is summed per step in FP32 over a lane's 16 units and
@@ -376,19 +376,24 @@ __device__ __forceinline__ float am_step(const f32x4* L, int lane, float Y, floa
 }
 
 // The sweep for one 64-path block, 16 paths (group t) at a time.  Lane
-// (g, n) ends with the results of path 16 g + n in q.
+// (g, n) ends with the results of path 16 g + n in q.  The block's state
+// buffer holds two segments ([segment parity][step][lane]): the forward
+// pass fills it with the last two segments, so only the segments before
+// them are recomputed, each into the slot its parity names.
 template <class Net, int ACT>
 __device__ __forceinline__ void am_block(const AdjArgs& a, const InstDev& I, const f32x4* L,
                                          int64_t blk, const float xr[4], const float lr[4],
                                          int lane, int g, int n, double (&q)[6]) {
-  const int M = I.M, k = a.ckpt, nseg = (M + k - 1) / k, ib_last = (nseg - 1) * k;
+  const int M = I.M, k = a.ckpt, nseg = (M + k - 1) / k;
+  const int ib_keep = (nseg > 2 ? nseg - 2 : 0) * k;  // first step whose state the forward keeps
   const int64_t N = I.N;
   const uint32_t tag = (uint32_t)I.tag;
   const bool clamp = I.clamp_zero != 0;
   const float K = I.K_f;
   float* ck = (float*)a.ckpt_buf;
-  // segment state of the block: [step][lane]
-  u32x4* const st = (u32x4*)a.state_buf + blk * (int64_t)k * 64 + lane;
+  u32x4* const st = (u32x4*)a.state_buf + blk * (int64_t)(2 * k) * 64 + lane;
+  // the lane's slot of step i
+  auto slot = [&](int i) { return st + (((i / k) & 1) * k + i % k) * 64; };
   for (int t = 0; t < 4; ++t) {
     if (blk * 64 + 16 * t >= N) break;
     const int64_t p = blk * 64 + 16 * t + n;
@@ -396,13 +401,13 @@ __device__ __forceinline__ void am_block(const AdjArgs& a, const InstDev& I, con
     const int64_t gp = I.path_offset + p;
     StepNormals nrm;
     // forward pass: checkpoints (every lane of a path writes, and later
-    // reads back, the same value), and the last segment's state
+    // reads back, the same value), and the last two segments' state
     float Y = I.Y0_f;
     for (int i = 0; i < M; ++i) {
       if (i % k == 0 && valid) ck[(int64_t)(i / k) * N + p] = Y;
       const float X = nrm.get(a, i, gp, tag, g, n);
-      if (i >= ib_last)
-        Y = am_step<Net, ACT, true>(L, lane, Y, X, xr, lr, clamp, st + (i - ib_last) * 64);
+      if (i >= ib_keep)
+        Y = am_step<Net, ACT, true>(L, lane, Y, X, xr, lr, clamp, slot(i));
       else
         Y = am_step<Net, ACT, false>(L, lane, Y, X, xr, lr, clamp, nullptr);
     }
@@ -411,14 +416,14 @@ __device__ __forceinline__ void am_block(const AdjArgs& a, const InstDev& I, con
     double thb[3] = {0.0, 0.0, 0.0};
     for (int seg = nseg - 1; seg >= 0; --seg) {
       const int ib = seg * k, ie = min(ib + k, M);
-      if (seg != nseg - 1) {
+      if (ib < ib_keep) {
         float Yc = valid ? ck[(int64_t)seg * N + p] : I.Y0_f;
         for (int i = ib; i < ie; ++i)
           Yc = am_step<Net, ACT, true>(L, lane, Yc, nrm.get(a, i, gp, tag, g, n), xr, lr, clamp,
-                                       st + (i - ib) * 64);
+                                       slot(i));
       }
       for (int i = ie - 1; i >= ib; --i) {
-        const u32x4 sv = st[(i - ib) * 64];
+        const u32x4 sv = *slot(i);
         const float X = nrm.get(a, i, gp, tag, g, n);
         // Lagrange basis at X over the lane's rows, as the forward
         // interpolation forms it
