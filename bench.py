@@ -254,12 +254,12 @@ def main():
     ga = W.CONFIGS["gbm_adjoint_2p22x16"]
     pr3 = S.Problem(ga["model"], ga["theta"], ga["Y0"], ga["T"], ga["M"], ga["m"], ga["N"], K=ga["K"])
     adj = {}
-    # algorithmic network flops of one sweep: forward pass over all M steps,
-    # recomputation of every segment but the last, and the reverse products
-    # (head transpose, three hidden transposes, first-layer reduction for Y
-    # and theta) at every step
+    # algorithmic network flops of one MFMA sweep: forward pass over all M
+    # steps, recomputation of every segment but the last two (whose state the
+    # forward pass keeps), and the reverse products (head transpose, three
+    # hidden transposes, first-layer reduction for Y and theta) at every step
     nseg = -(-ga["M"] // ga["ckpt"])
-    fwd_evals = ga["M"] + (nseg - 1) * ga["ckpt"]
+    fwd_evals = ga["M"] + max(nseg - 2, 0) * ga["ckpt"]
     rev_flops = 2 * (64 * ga["m"] + 3 * 64 * 64 + 64 * (1 + 2))  # Y and (sigma, mu)
     adj_flops = ga["N"] * (fwd_evals * FLOPS_PER_PATH_STEP + ga["M"] * rev_flops)
     for prec in ("f64", "f32", "bf16x3", "pwl64", "pwl32"):
