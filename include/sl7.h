@@ -279,11 +279,11 @@ typedef struct {
 
 /* Workspace size (bytes) for sl7_adjoint: checkpoints
  * ceil(M / ckpt_every) x N states, the per-step evaluation state of the
- * steps kept at once (ckpt_every x N x 32 bytes: one segment's ReLU masks
- * in the FP64 lane sweep, two segments of 16-byte lane records in the MFMA
- * sweeps; 4 bytes of piece index in the PWL modes; the analytic map needs
- * none but the size does not depend on H) plus block sums.  0 for bad
- * arguments. */
+ * steps kept at once (in F32 and BF16X3 ckpt_every x N x 128 bytes: two
+ * segments of 16-byte records for each of a path's four lanes; in F64
+ * ckpt_every x N x 32 bytes: one segment's ReLU masks; in the PWL modes 4
+ * bytes of piece index per path-step; the analytic map needs none but the
+ * size does not depend on H) plus block sums.  0 for bad arguments. */
 size_t sl7_adjoint_ws_bytes(const sl7_problem* pr, int prec, int ckpt_every);
 
 /* H == NULL: analytic map (GBM, OU).  prec: SL7_F64, SL7_F32 or SL7_BF16X3

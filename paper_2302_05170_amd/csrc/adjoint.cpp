@@ -26,7 +26,11 @@ WsLayout layout_of(const sl7_problem* pr, int prec, int ckpt) {
   const size_t el = (prec == SL7_F64 || prec == SL7_PWL64) ? sizeof(double) : sizeof(float);
   const int64_t nseg = (pr->M + ckpt - 1) / ckpt;
   const int64_t nb = (pr->N + 63) / 64;
-  const int words = adjoint_state_words(is_pwl(prec) ? 2 : 1);
+  // the MFMA sweeps keep two segments of 16-byte lane records for each of a
+  // block's four 16-path groups (32 words per lane-step); the lane sweeps
+  // one segment of their per-path state
+  const int words = (prec == SL7_F32 || prec == SL7_BF16X3) ? 32
+                                                           : adjoint_state_words(is_pwl(prec) ? 2 : 1);
   WsLayout L;
   L.ckpt = 0;
   L.state = align256(el * (size_t)nseg * (size_t)pr->N);

@@ -18,11 +18,13 @@
 // and theta (eq. 6.3/6.4 with the inputs (Y, dt, theta)), reduces the
 // cotangent of its pre-activation against the weights of Y and of theta.
 //
-// Sweep per 16-path group (Algorithm I, steps 3-6, then backwards): the
+// Sweep per 64-path block (Algorithm I, steps 3-6, then backwards): the
 // forward pass stores Y every `ckpt` steps and, for the steps of the last
 // two segments, the evaluation state (ReLU masks, the state Y_i for
-// Softplus, the clamp flag); each earlier segment is recomputed from its
-// checkpoint with the same Philox counters before its reverse steps.  Softplus
+// Softplus, the clamp flag); the reverse sweep takes the paths whose payoff
+// derivative at Y_T is nonzero, packed into 16-path groups, and recomputes
+// each earlier segment from its checkpoint with the same Philox counters
+// before its reverse steps.  Softplus
 // recomputes the pre-activations of a step from Y_i in its reverse step for
 // the logistic derivative.  lambda = dY_T/dY_i runs backwards in FP32; the
 // theta-cotangent is summed per step in FP32 over a lane's 16 units and
@@ -375,55 +377,120 @@ __device__ __forceinline__ float am_step(const f32x4* L, int lane, float Y, floa
   return Yn;
 }
 
-// The sweep for one 64-path block, 16 paths (group t) at a time.  Lane
-// (g, n) ends with the results of path 16 g + n in q.  The block's state
-// buffer holds two segments ([segment parity][step][lane]): the forward
-// pass fills it with the last two segments, so only the segments before
-// them are recomputed, each into the slot its parity names.
+// Lanes below the calling lane whose bit is set in the wave mask m.
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// A double moved to the lane `to` names (every lane sends one, every lane
+// receives one: `to` is a permutation of the wave's lanes).
+__device__ __forceinline__ double push_double(int to, double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute(to << 2, (int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_permute(to << 2, (int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// The sweep for one 64-path block.
+//   Forward: the block's four 16-path groups each run all M steps, storing
+//   Y every k steps and each step's state for the last two segments in the
+//   block's state buffer ([group][segment parity][step][lane]).
+//   Reverse: only paths whose payoff has a nonzero derivative at Y_T take
+//   part (for the call, Y_T > K; for Y_T, every path): a path with
+//   f'(Y_T) = 0 has zero pathwise sensitivities, and its sweep is skipped.
+//   Those paths are packed, in block order, into as few 16-path groups as
+//   they fill; each packed lane reads and writes its path's own state
+//   slots, so the forward pass's segments serve the packed groups, and the
+//   segments before them are recomputed from the checkpoints.
+// Lane sums (lane l = path l for f; lanes of group row g = 0 for the
+// sensitivities, packed order) go to sum / sum2; per-path records to
+// a.per_path.
 template <class Net, int ACT>
 __device__ __forceinline__ void am_block(const AdjArgs& a, const InstDev& I, const f32x4* L,
                                          int64_t blk, const float xr[4], const float lr[4],
-                                         int lane, int g, int n, double (&q)[6]) {
+                                         int lane, int g, int n, double (&sum)[6],
+                                         double (&sum2)[6]) {
   const int M = I.M, k = a.ckpt, nseg = (M + k - 1) / k;
   const int ib_keep = (nseg > 2 ? nseg - 2 : 0) * k;  // first step whose state the forward keeps
-  const int64_t N = I.N;
+  const int64_t N = I.N, base = blk * 64;
   const uint32_t tag = (uint32_t)I.tag;
   const bool clamp = I.clamp_zero != 0;
   const float K = I.K_f;
+  const int nq = 2 + a.n_theta;
   float* ck = (float*)a.ckpt_buf;
-  u32x4* const st = (u32x4*)a.state_buf + blk * (int64_t)(2 * k) * 64 + lane;
-  // the lane's slot of step i
-  auto slot = [&](int i) { return st + (((i / k) & 1) * k + i % k) * 64; };
+  u32x4* const st0 = (u32x4*)a.state_buf + blk * (int64_t)(8 * k) * 64;
+  // slot of step i of group t for lane ln
+  auto slot = [&](int t, int i, int ln) {
+    return st0 + ((2 * t + ((i / k) & 1)) * k + i % k) * 64 + ln;
+  };
+  // forward pass of the four groups; lane l keeps f and the activity of path l
+  double f_own = 0.0;
+  bool act_own = false;
   for (int t = 0; t < 4; ++t) {
-    if (blk * 64 + 16 * t >= N) break;
-    const int64_t p = blk * 64 + 16 * t + n;
+    if (base + 16 * t >= N) break;
+    const int64_t p = base + 16 * t + n;
     const bool valid = p < N;
     const int64_t gp = I.path_offset + p;
     StepNormals nrm;
-    // forward pass: checkpoints (every lane of a path writes, and later
-    // reads back, the same value), and the last two segments' state
+    // checkpoints: every lane of a path writes, and later reads back, the
+    // same value
     float Y = I.Y0_f;
     for (int i = 0; i < M; ++i) {
       if (i % k == 0 && valid) ck[(int64_t)(i / k) * N + p] = Y;
       const float X = nrm.get(a, i, gp, tag, g, n);
       if (i >= ib_keep)
-        Y = am_step<Net, ACT, true>(L, lane, Y, X, xr, lr, clamp, slot(i));
+        Y = am_step<Net, ACT, true>(L, lane, Y, X, xr, lr, clamp, slot(t, i, lane));
       else
         Y = am_step<Net, ACT, false>(L, lane, Y, X, xr, lr, clamp, nullptr);
     }
-    const double f = a.payoff == 0 ? (double)Y : fmax((double)Y - (double)K, 0.0);
-    float lam = a.payoff == 0 ? 1.f : (Y > K ? 1.f : 0.f);
+    if (g == t && valid) {
+      f_own = a.payoff == 0 ? (double)Y : fmax((double)Y - (double)K, 0.0);
+      act_own = a.payoff == 0 || Y > K;
+    }
+  }
+  sum[0] = f_own;
+  sum2[0] = f_own * f_own;
+  const int64_t p_own = base + lane;
+  if (a.per_path && p_own < N && !act_own) {
+    a.per_path[p_own * nq] = f_own;
+    for (int t = 1; t < nq; ++t) a.per_path[p_own * nq + t] = 0.0;
+  }
+  // the packed lanes read state and checkpoints other lanes of this wave
+  // wrote (a wave's memory operations are in order; the fence keeps the
+  // compiler from moving accesses across this point)
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  // pack the active paths: lane j < cnt receives the block lane of the j-th
+  // active path, and its f
+  const uint64_t am = __ballot(act_own);
+  const int cnt = __popcll(am);
+  const int to = act_own ? lanes_below(am) : cnt + lanes_below(~am);
+  const int src = __builtin_amdgcn_ds_permute(to << 2, lane);
+  const double f_src = push_double(to, f_own);
+  // reverse sweep of the packed groups
+  for (int c = 0; c < (cnt + 15) / 16; ++c) {
+    const int j = 16 * c + n;
+    const bool valid = j < cnt;
+    // the path of packed slot j (a lane past the last active path repeats
+    // slot 16 c's path: same values into the same slots, results unused)
+    const int l0 = __shfl(src, valid ? j : 16 * c);
+    const double fj = __shfl(f_src, valid ? j : 16 * c);
+    const int t0 = l0 >> 4, ln0 = 16 * g + (l0 & 15);
+    const int64_t p = base + l0;
+    const int64_t gp = I.path_offset + p;
+    StepNormals nrm;
+    float lam = 1.f;  // f'(Y_T) of an active path
     double thb[3] = {0.0, 0.0, 0.0};
     for (int seg = nseg - 1; seg >= 0; --seg) {
       const int ib = seg * k, ie = min(ib + k, M);
       if (ib < ib_keep) {
-        float Yc = valid ? ck[(int64_t)seg * N + p] : I.Y0_f;
+        float Yc = ck[(int64_t)seg * N + p];
         for (int i = ib; i < ie; ++i)
           Yc = am_step<Net, ACT, true>(L, lane, Yc, nrm.get(a, i, gp, tag, g, n), xr, lr, clamp,
-                                       slot(i));
+                                       slot(t0, i, ln0));
       }
       for (int i = ie - 1; i >= ib; --i) {
-        const u32x4 sv = *slot(i);
+        const u32x4 sv = *slot(t0, i, ln0);
         const float X = nrm.get(a, i, gp, tag, g, n);
         // Lagrange basis at X over the lane's rows, as the forward
         // interpolation forms it
@@ -461,12 +528,17 @@ __device__ __forceinline__ void am_block(const AdjArgs& a, const InstDev& I, con
     }
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk) thb[kk] = path_sum(thb[kk]);
-    if (g == t) {
-      q[0] = f;
-      q[1] = (double)lam;
-      q[2] = thb[0];
-      q[3] = thb[1];
-      q[4] = thb[2];
+    if (g == 0 && valid) {
+      const double r[4] = {(double)lam, thb[0], thb[1], thb[2]};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        sum[1 + t] += r[t];
+        sum2[1 + t] += r[t] * r[t];
+      }
+      if (a.per_path) {
+        a.per_path[p * nq] = fj;
+        for (int t = 1; t < nq; ++t) a.per_path[p * nq + t] = r[t - 1];
+      }
     }
   }
 }
@@ -486,26 +558,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_adjoint_mfma(AdjArgs a, const u3
   const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
   float xr[4], lr[4];
   lane_rows(a, a.m, g, xr, lr);
-  const int64_t N = I.N;
   const int64_t wstride = (int64_t)gridDim.x * WAVES;
   for (int64_t blk = (int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6); blk < n_blocks;
        blk += wstride) {
-    double q[6] = {0, 0, 0, 0, 0, 0};
-    am_block<Net, ACT>(a, I, L, blk, xr, lr, lane, g, n, q);
-    // lane l now holds path l of the block
-    const int64_t p = blk * 64 + lane;
-    const bool valid = p < N;
-    if (!valid)
-      for (int t = 0; t < 6; ++t) q[t] = 0.0;
-    const int nq = 2 + a.n_theta;
-    if (a.per_path && valid)
-      for (int t = 0; t < nq; ++t) a.per_path[p * nq + t] = q[t];
-    double s[6], s2[6];
-#pragma unroll
-    for (int t = 0; t < 6; ++t) {
-      s[t] = q[t];
-      s2[t] = q[t] * q[t];
-    }
+    double s[6] = {0, 0, 0, 0, 0, 0}, s2[6] = {0, 0, 0, 0, 0, 0};
+    am_block<Net, ACT>(a, I, L, blk, xr, lr, lane, g, n, s, s2);
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1)
 #pragma unroll

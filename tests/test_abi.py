@@ -181,14 +181,16 @@ def test_narrow_softplus_network_rejected_by_piecewise_linear_adjoint(L):
 def test_adjoint_workspace_size(L):
     """sl7_adjoint_ws_bytes covers its documented parts: ceil(M / k) x N
     checkpoints (8 or 4 bytes), k x N x 32 bytes of per-step network state
-    (4 bytes of piece index in the PWL modes) and one 96-byte partial per
-    64-path block; 0 for bad arguments."""
+    in FP64 (k x N x 128 in the MFMA modes F32 and BF16X3, 4 bytes of piece
+    index in the PWL modes) and one 96-byte partial per 64-path block; 0 for
+    bad arguments."""
     import paper_2302_05170_amd as S
     f = L.lib().sl7_adjoint_ws_bytes
     for N, M, k in ((1, 1, 1), (1000, 16, 4), (2 ** 22, 16, 4), (4097, 7, 3), (64, 32, 32)):
         pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, M, 5, N).c()
         nseg, nb = -(-M // k), -(-N // 64)
-        for prec, el, words in ((L.F64, 8, 8), (L.F32, 4, 8), (L.PWL64, 8, 1), (L.PWL32, 4, 1)):
+        for prec, el, words in ((L.F64, 8, 8), (L.F32, 4, 32), (L.BF16X3, 4, 32), (L.PWL64, 8, 1),
+                                (L.PWL32, 4, 1)):
             need = el * nseg * N + 4 * words * k * 64 * nb + 96 * nb
             got = f(ctypes.byref(pr), prec, k)
             assert need <= got <= need + 4 * 256, (N, M, k, prec, got, need)
