@@ -220,6 +220,9 @@ def main():
                 S.adjoint(pra, H, prec=prec, seed=ga["seed"], payoff=1, ckpt_every=ga["ckpt"])
             torch.cuda.synchronize()
             log(f"profile run: {args.steps} adjoint sweeps in {prec}, N={ga['N']}, M={ga['M']}")
+            _, yt = S.simulate(pra, H, prec="f32" if prec != "bf16x3" else prec, seed=ga["seed"],
+                               want_yt=True)
+            log(f"active paths (Y_T > K): {int((yt > ga['K']).sum().item())} of {ga['N']}")
             return
         plan = None
         if args.grab is not None:
@@ -258,10 +261,15 @@ def main():
     # steps, recomputation of every segment but the last two (whose state the
     # forward pass keeps), and the reverse products (head transpose, three
     # hidden transposes, first-layer reduction for Y and theta) at every step
+    # for the paths whose call payoff has a nonzero derivative at Y_T (the
+    # others' sensitivities are zero and the MFMA sweeps skip their reverse)
     nseg = -(-ga["M"] // ga["ckpt"])
-    fwd_evals = ga["M"] + max(nseg - 2, 0) * ga["ckpt"]
+    _, yt3 = S.simulate(pr3, H, prec="f32", seed=ga["seed"], want_yt=True)
+    n_active = int((yt3 > ga["K"]).sum().item())
     rev_flops = 2 * (64 * ga["m"] + 3 * 64 * 64 + 64 * (1 + 2))  # Y and (sigma, mu)
-    adj_flops = ga["N"] * (fwd_evals * FLOPS_PER_PATH_STEP + ga["M"] * rev_flops)
+    adj_flops = (ga["N"] * ga["M"] * FLOPS_PER_PATH_STEP +
+                 n_active * (max(nseg - 2, 0) * ga["ckpt"] * FLOPS_PER_PATH_STEP +
+                             ga["M"] * rev_flops))
     for prec in ("f64", "f32", "bf16x3", "pwl64", "pwl32"):
         S.adjoint(pr3, H, prec=prec, seed=ga["seed"], payoff=1, ckpt_every=ga["ckpt"])
         torch.cuda.synchronize()
@@ -274,6 +282,7 @@ def main():
         adj[prec] = {"s_per_greek": dt / len(g["grad"]), "seconds": dt, "greeks": g["grad"],
                      "greeks_se": g["grad_se"]}
         if prec in ("f32", "bf16x3"):
+            adj[prec]["active_paths"] = n_active
             adj[prec]["alg_tflops"] = adj_flops / dt / 1e12
             adj[prec]["frac_of_dtype_peak"] = adj_flops / dt / PEAK[prec]
         log(f"adjoint {prec}: {dt:.4f} s (median of 3) for {len(g['grad'])} Greeks {g['grad']}")
