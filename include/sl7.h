@@ -211,13 +211,14 @@ int sl7_simulate(const sl7_problem* pr, const sl7_mlp* H, int prec,
  * y_kj = map(s_k over dt)_j; each path takes y_j(Y_i) by barycentric
  * interpolation in Y over the s_k (a global interpolation instead of a
  * per-path network call) and then Y_{i+1} = g_m(X) as in 7L.  Step 0
- * uses map(Y0 over dt).  The tables are built on the host in FP64 (m + m^2
- * map evaluations per step); the per-path work runs one path per lane in
- * prec SL7_F64 or SL7_F32 (others: SL7_EUNSUPPORTED).  Problem, seed
- * (same normals as sl7_simulate), YT_dev and stats_host as in sl7_simulate;
- * stats_host->n_out_of_domain counts the table's network inputs outside
- * the training domain.  SL7_ENUMERIC when two marginal points of a step
- * coincide. */
+ * uses map(Y0 over dt).  The tables are built on the GPU in FP64 (m + 1
+ * map evaluations per step, one workgroup per step); the per-path work runs
+ * one path per lane in prec SL7_F64 or SL7_F32 (others: SL7_EUNSUPPORTED).
+ * Problem, seed (same normals as sl7_simulate), YT_dev and stats_host as in
+ * sl7_simulate; stats_host->n_out_of_domain counts the table's network
+ * inputs outside the training domain.  Synchronises `stream` (the table
+ * checks): SL7_ENUMERIC when two marginal points of a step coincide or a
+ * table entry is not finite. */
 int sl7_simulate_cdc(const sl7_problem* pr, const sl7_mlp* H, int prec, uint64_t seed,
                      void* YT_dev, sl7_stats* stats_host, void* stream);
 

@@ -1,6 +1,6 @@
-// Host side of the 7L-CDC variant: the per-step tables of marginal and
-// conditional collocation points (FP64, once per call), their upload, the
-// per-lane kernel and the statistics.
+// Host side of the 7L-CDC variant: the launch of the per-step table kernel
+// (FP64, on the GPU), of the per-lane kernel and of the statistics, and the
+// table checks.
 //
 // Reading of the variant (the paper describes it in outline only: Numerical
 // Results, the paragraph after Table 6.1, and the Parallelization section):
@@ -8,8 +8,8 @@
 //     map over [0, t_i] from Y0, s_k = H(Y0, t_i, theta)_k: the points of the
 //     law of Y(t_i) given Y(0) = Y0;
 //   - the conditional collocation points are computed only at them,
-//     y_kj = H(s_k, dt, theta)_j (m map evaluations per step instead of one
-//     per path);
+//     y_kj = H(s_k, dt, theta)_j (m + 1 map evaluations per step instead of
+//     one per path);
 //   - a path at Y_i takes y_j = sum_k l_k(Y_i) y_kj (Lagrange basis over the
 //     s_k, barycentric form), then Y_{i+1} = g_m(X): two interpolations a step;
 //   - step 0 starts from the point mass at Y0: y_j = H(Y0, dt, theta)_j.
@@ -18,8 +18,8 @@
 
 #include <cmath>
 #include <cstring>
-#include <vector>
 
+#include "cdc_tables.hpp"
 #include "sl7_host.hpp"
 
 namespace sl7 {
@@ -27,98 +27,6 @@ namespace sl7 {
 hipError_t launch_sim_cdc(int prec, const SimArgs& a, const void* tab, int64_t n_blocks,
                           hipStream_t s);
 
-namespace {
-
-constexpr int cdc_stride(int m) { return 2 * m + m * m; }
-
-// The network in FP64 on the host: inputs (Y, h, theta) through the stored
-// input affine, hidden layers with the stored activation, linear head.
-void net_forward(const Mlp& H, const sl7_problem& pr, double Y, double h, double* y) {
-  const sl7_mlp_desc& d = H.d;
-  double in[SL7_MAX_DIN] = {Y, h};
-  for (int k = 0; k < n_theta(pr.model); ++k) in[2 + k] = pr.theta[k];
-  double a[64], z[64];
-  for (int k = 0; k < d.d_in; ++k) a[k] = d.in_scale[k] * in[k] + d.in_shift[k];
-  int n_in = d.d_in;
-  for (int l = 0; l <= d.depth; ++l) {
-    const int n_out = l == d.depth ? d.m : d.width;
-    for (int o = 0; o < n_out; ++o) {
-      double s = H.b(l, o);
-      for (int k = 0; k < n_in; ++k) s += (double)H.W(l, o, k) * a[k];
-      z[o] = s;
-    }
-    for (int o = 0; o < n_out; ++o) {
-      if (l == d.depth) a[o] = z[o];
-      else if (d.act == SL7_RELU) a[o] = z[o] > 0.0 ? z[o] : 0.0;
-      else a[o] = (z[o] > 0.0 ? z[o] : 0.0) + std::log1p(std::exp(-std::fabs(z[o])));
-    }
-    n_in = n_out;
-  }
-  for (int j = 0; j < d.m; ++j) y[j] = a[j];
-}
-
-// The analytic map over a horizon h: GBM's lognormal law, OU's Gaussian law
-// (eq. 6.6).
-void analytic_map(const sl7_problem& pr, const double* x, double Y, double h, double* y) {
-  if (pr.model == SL7_GBM) {
-    const double sig = pr.theta[0], mu = pr.theta[1];
-    for (int j = 0; j < pr.m; ++j)
-      y[j] = Y * std::exp((mu - 0.5 * sig * sig) * h + sig * std::sqrt(h) * x[j]);
-  } else {
-    const double ybar = pr.theta[0], sig = pr.theta[1], lam = pr.theta[2];
-    const double e = std::exp(-lam * h);
-    const double sd = sig * std::sqrt((1.0 - std::exp(-2.0 * lam * h)) / (2.0 * lam));
-    for (int j = 0; j < pr.m; ++j) y[j] = Y * e + ybar * (1.0 - e) + sd * x[j];
-  }
-}
-
-// Builds the tables: row i = (s[m], lam[m], y[m][m]); row 0 holds Y0 and the
-// conditional points at Y0 in k = 0.  *n_ood counts network inputs outside
-// the training domain.
-int cdc_tables(const sl7_problem& pr, const Mlp* H, const double* x, std::vector<double>& tab,
-               int64_t* n_ood) {
-  const int m = pr.m, M = pr.M, st = cdc_stride(m);
-  const double dt = pr.T / M;
-  tab.assign((size_t)M * st, 0.0);
-  *n_ood = 0;
-  auto map = [&](double Y, double h, double* y) {
-    if (H) {
-      if (Y < H->d.dom_lo[0] || Y > H->d.dom_hi[0]) ++*n_ood;
-      net_forward(*H, pr, Y, h, y);
-    } else {
-      analytic_map(pr, x, Y, h, y);
-    }
-  };
-  for (int i = 0; i < M; ++i) {
-    double* s = tab.data() + (size_t)i * st;
-    double* lam = s + m;
-    double* y = s + 2 * m;
-    if (i == 0) {
-      for (int k = 0; k < m; ++k) s[k] = pr.Y0;
-      map(pr.Y0, dt, y);
-      continue;
-    }
-    const double ti = i * pr.T / M;
-    map(pr.Y0, ti, s);
-    for (int k = 0; k < m; ++k) {
-      double prod = 1.0;
-      for (int l = 0; l < m; ++l) {
-        if (l == k) continue;
-        if (s[k] == s[l])
-          return fail(SL7_ENUMERIC, "7L-CDC: marginal collocation points of step %d are not "
-                                    "distinct", i);
-        prod *= s[k] - s[l];
-      }
-      lam[k] = 1.0 / prod;
-    }
-    for (int k = 0; k < m; ++k) map(s[k], dt, y + k * m);
-  }
-  for (double v : tab)
-    if (!std::isfinite(v)) return fail(SL7_ENUMERIC, "7L-CDC: non-finite table entry");
-  return SL7_OK;
-}
-
-}  // namespace
 }  // namespace sl7
 
 using namespace sl7;
@@ -133,15 +41,10 @@ extern "C" int sl7_simulate_cdc(const sl7_problem* pr, const sl7_mlp* Hc, int pr
   double x[SL7_MAX_M], w[SL7_MAX_M];
   rc = gh_nodes(pr->m, x, w);
   if (rc) return rc;
-  std::vector<double> tab;
-  int64_t n_ood = 0;
   if (H) {
-    std::lock_guard<std::mutex> lk(H->mu);
-    rc = cdc_tables(*pr, H, x, tab, &n_ood);
-  } else {
-    rc = cdc_tables(*pr, nullptr, x, tab, &n_ood);
+    rc = H->ensure_device(SL7_F64);  // the FP64 layout the table kernel evaluates
+    if (rc) return rc;
   }
-  if (rc) return rc;
   int dev;
   rc = current_device(&dev);
   if (rc) return rc;
@@ -153,26 +56,61 @@ extern "C" int sl7_simulate_cdc(const sl7_problem* pr, const sl7_mlp* Hc, int pr
   SimArgs a;
   rc = prepare_instances(pr, 1, H, prec, seed, YT_dev, s, ws, a);
   if (rc) return rc;
-  const size_t n = tab.size();
-  const size_t bytes = prec == SL7_F64 ? n * sizeof(double) : n * sizeof(float);
-  rc = ws.cdc.reserve(bytes);
-  if (!rc) rc = ws.stage_cdc.acquire(bytes);
+  const int m = pr->m, st = cdc_stride(m);
+  const size_t n = (size_t)pr->M * st;
+  const size_t off32 = (n * sizeof(double) + 255) & ~size_t(255);
+  const size_t offf = (off32 + n * sizeof(float) + 255) & ~size_t(255);
+  rc = ws.cdc.reserve(offf + 4 * sizeof(unsigned long long));
   if (rc) return rc;
-  if (prec == SL7_F64) {
-    std::memcpy(ws.stage_cdc.p, tab.data(), bytes);
-  } else {
-    float* f = (float*)ws.stage_cdc.p;
-    for (size_t i = 0; i < n; ++i) f[i] = (float)tab[i];
+  char* base = (char*)ws.cdc.p;
+  CdcTabArgs t;
+  std::memset(&t, 0, sizeof(t));
+  if (H) {
+    t.net = (const double*)H->net64->p;
+    t.w0full = (const double*)H->w0full->p;
+    t.d_in = H->d.d_in;
+    t.act = H->d.act;
+    t.dom_lo = H->d.dom_lo[0];
+    t.dom_hi = H->d.dom_hi[0];
   }
-  rc = ws.stage_cdc.upload(ws.cdc.p, 0, bytes, s, "hipMemcpyAsync(7L-CDC tables)");
-  if (rc) return rc;
-  hipError_t e = launch_sim_cdc(prec, a, ws.cdc.p, (pr->N + 63) / 64, s);
+  t.m = m;
+  t.M = pr->M;
+  t.model = pr->model;
+  t.n_theta = n_theta(pr->model);
+  t.Y0 = pr->Y0;
+  t.T = pr->T;
+  t.dt = pr->T / pr->M;
+  for (int k = 0; k < 4; ++k) t.theta[k] = pr->theta[k];
+  for (int j = 0; j < m; ++j) t.x[j] = x[j];
+  t.tab64 = (double*)base;
+  t.tab32 = prec == SL7_F32 ? (float*)(base + off32) : nullptr;
+  t.flags = (unsigned long long*)(base + offf);
+  hipError_t e = launch_zero_u64(t.flags, 3, s);
+  if (e == hipSuccess) e = launch_cdc_tables(t, s);
+  if (e != hipSuccess) return hip_fail(e, "launch 7L-CDC tables");
+  e = launch_sim_cdc(prec, a, prec == SL7_F64 ? (const void*)t.tab64 : (const void*)t.tab32,
+                     (pr->N + 63) / 64, s);
   if (e != hipSuccess) return hip_fail(e, "launch 7L-CDC kernel");
   e = launch_finalize(a.partials, a.inst, 1, ws.chunks.p, (sl7_stats*)ws.stats.p, s);
   if (e != hipSuccess) return hip_fail(e, "launch finalize");
-  if (!stats_host) return SL7_OK;
-  rc = fetch_stats(ws, 1, stats_host, s);
+  // the table checks: the flags come back with the statistics (one wait)
+  rc = ws.stage_cdc.acquire(3 * sizeof(unsigned long long));
   if (rc) return rc;
-  stats_host->n_out_of_domain = n_ood;
+  unsigned long long* fl = (unsigned long long*)ws.stage_cdc.p;
+  e = hipMemcpyAsync(fl, t.flags, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_fail(e, "copy 7L-CDC table flags");
+  sl7_stats st_tmp;
+  rc = stats_host ? fetch_stats(ws, 1, &st_tmp, s) : SL7_OK;
+  if (!stats_host) {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "synchronise 7L-CDC");
+  }
+  if (fl[0]) return fail(SL7_ENUMERIC, "7L-CDC: marginal collocation points of %llu step(s) are not distinct", fl[0]);
+  if (fl[1]) return fail(SL7_ENUMERIC, "7L-CDC: non-finite table entries in %llu place(s)", fl[1]);
+  if (rc) return rc;
+  if (stats_host) {
+    *stats_host = st_tmp;
+    stats_host->n_out_of_domain = (int64_t)fl[2];
+  }
   return SL7_OK;
 }

@@ -16,12 +16,6 @@
 
 namespace sl7 {
 
-template <typename T>
-__device__ __forceinline__ T act_fn(int act, T z) {
-  if (act == SL7_RELU) return z > T(0) ? z : T(0);
-  return z > T(0) ? z + log1p(exp(-z)) : log1p(exp(z));
-}
-
 // Barycentric interpolation, second form, with the exact-node branch.
 template <typename T>
 __device__ __forceinline__ T bary_lane(const T* xs, const T* ls, int m, const T y[kMaxM], T X) {
@@ -254,10 +248,7 @@ hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Batched network evaluation in double, one input row per lane: h0 = in_scale
-// * in + in_shift, then the layers exactly as in eq. (6.3)/(6.4).  w0full:
-// [in_scale (d_in), in_shift (d_in), W0 (64 x d_in), b0 (64)], net: the lane
-// layout above (its wY part unused here).
+// Batched network evaluation in double, one input row per lane (net_eval64).
 __global__ __launch_bounds__(64) void k_eval_lane(const double* __restrict__ net,
                                                   const double* __restrict__ w0full, int d_in,
                                                   int m, int act, const float* __restrict__ in,
@@ -267,43 +258,12 @@ __global__ __launch_bounds__(64) void k_eval_lane(const double* __restrict__ net
   const int64_t row = block_index() * 64 + lane;
   if (row - lane >= B) return;
   const bool valid = row < B;
-  double h0[kMaxDinLane];
-  for (int k = 0; k < kMaxDinLane; ++k) h0[k] = 0.0;
+  double x[kMaxDinLane], y[kMaxM];
 #pragma unroll
-  for (int k = 0; k < kMaxDinLane; ++k)
-    if (k < d_in) h0[k] = valid ? w0full[k] * (double)in[row * d_in + k] + w0full[d_in + k] : 0.0;
-  const double* W0 = w0full + 2 * d_in;
-  const double* b0 = W0 + 64 * d_in;
-  double* hA = lds_h + lane;
-  double* hB = lds_h + 64 * 64 + lane;
-  for (int o = 0; o < 64; ++o) {
-    double s = b0[o];
-#pragma unroll
-    for (int k = 0; k < kMaxDinLane; ++k)
-      if (k < d_in) s = fma(W0[o * d_in + k], h0[k], s);
-    hA[o * 64] = act_fn(act, s);
-  }
-  const double* Wl = net + 64;
-  double* hin = hA;
-  double* hout = hB;
-  for (int l = 0; l < 3; ++l) {
-    const double* bl = Wl + 64 * 64;
-    for (int o = 0; o < 64; ++o) {
-      double s = bl[o];
-      const double* r = Wl + o * 64;
-      for (int k = 0; k < 64; ++k) s = fma(r[k], hin[k * 64], s);
-      hout[o * 64] = act_fn(act, s);
-    }
-    Wl += 64 * 64 + 64;
-    double* t = hin; hin = hout; hout = t;
-  }
-  const double* bh = Wl + 64 * m;
-  for (int j = 0; j < m; ++j) {
-    double s = bh[j];
-    const double* r = Wl + j * 64;
-    for (int k = 0; k < 64; ++k) s = fma(r[k], hin[k * 64], s);
-    if (valid) out[row * m + j] = (float)s;
-  }
+  for (int k = 0; k < kMaxDinLane; ++k) x[k] = (valid && k < d_in) ? (double)in[row * d_in + k] : 0.0;
+  net_eval64(net, w0full, d_in, m, act, x, y, lds_h + lane, lds_h + 64 * 64 + lane);
+  for (int j = 0; j < m; ++j)
+    if (valid) out[row * m + j] = (float)y[j];
 }
 
 hipError_t launch_eval_lane(const double* net, const double* w0full, int d_in, int m, int act,

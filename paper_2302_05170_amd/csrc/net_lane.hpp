@@ -16,6 +16,7 @@
 #include <stdint.h>
 
 #include "../../include/sl7.h"
+#include "sl7_internal.hpp"
 
 namespace sl7 {
 
@@ -437,6 +438,59 @@ __device__ __forceinline__ T lane_net_vjp_softplus(const void* net, const void* 
     if (l > 0) dense64<T, true>(W + kLaneWy + (l - 1) * kLaneLayer, d, stage);
   }
   return first_layer_vjp<T>(W, wthv, n_theta, d, thb);
+}
+
+template <typename T>
+__device__ __forceinline__ T act_fn(int act, T z) {
+  if (act == SL7_RELU) return z > T(0) ? z : T(0);
+  return z > T(0) ? z + log1p(exp(-z)) : log1p(exp(z));
+}
+
+// The network at one raw input x (d_in values) in double, one input per
+// lane: h0 = in_scale * x + in_shift, then the layers of eq. (6.3)/(6.4).
+// w0full: [in_scale (d_in), in_shift (d_in), W0 (64 x d_in), b0 (64)]; net:
+// [wY (64, unused here), then per hidden layer W (64 x 64, row-major) and
+// b (64), then W_head (m x 64) and b_head (m)].  hA, hB: this lane's two
+// LDS columns of 64 doubles, stride 64.  y: the m outputs.
+__device__ __forceinline__ void net_eval64(const double* __restrict__ net,
+                                           const double* __restrict__ w0full, int d_in, int m,
+                                           int act, const double* x, double* y, double* hA,
+                                           double* hB) {
+  double h0[kMaxDinLane];
+#pragma unroll
+  for (int k = 0; k < kMaxDinLane; ++k) h0[k] = k < d_in ? w0full[k] * x[k] + w0full[d_in + k] : 0.0;
+  const double* W0 = w0full + 2 * d_in;
+  const double* b0 = W0 + 64 * d_in;
+  for (int o = 0; o < 64; ++o) {
+    double s = b0[o];
+#pragma unroll
+    for (int k = 0; k < kMaxDinLane; ++k)
+      if (k < d_in) s = fma(W0[o * d_in + k], h0[k], s);
+    hA[o * 64] = act_fn(act, s);
+  }
+  const double* Wl = net + 64;
+  double* hin = hA;
+  double* hout = hB;
+  for (int l = 0; l < 3; ++l) {
+    const double* bl = Wl + 64 * 64;
+    for (int o = 0; o < 64; ++o) {
+      double s = bl[o];
+      const double* r = Wl + o * 64;
+      for (int k = 0; k < 64; ++k) s = fma(r[k], hin[k * 64], s);
+      hout[o * 64] = act_fn(act, s);
+    }
+    Wl += 64 * 64 + 64;
+    double* t = hin;
+    hin = hout;
+    hout = t;
+  }
+  const double* bh = Wl + 64 * m;
+  for (int j = 0; j < m; ++j) {
+    double s = bh[j];
+    const double* r = Wl + j * 64;
+    for (int k = 0; k < 64; ++k) s = fma(r[k], hin[k * 64], s);
+    y[j] = s;
+  }
 }
 
 }  // namespace sl7

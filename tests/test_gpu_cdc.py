@@ -180,3 +180,28 @@ def test_16_bit_modes_refused(S):
     pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 4, 5, 100)
     with pytest.raises(L.Sl7Error, match="F64 or F32"):
         S.simulate_cdc(pr, H, prec="bf16x3", seed=1)
+
+
+def test_coinciding_marginal_points_are_reported(S, tmp_path):
+    """A network whose outputs all equal 1 maps Y0 to coinciding marginal
+    points: the table kernel counts them and the call returns SL7_ENUMERIC
+    (the per-lane kernel meanwhile runs on infinite weights without fault)."""
+    from paper_2302_05170_amd import _lib as L
+    Ho = oracle.load_mlp(GBM_WEIGHTS)
+    Wf = [np.array(w) for w in Ho.W]
+    bf = [np.array(v) for v in Ho.b]
+    Wf[-1][:] = 0.0
+    bf[-1][:] = 1.0
+    flat = oracle.Mlp(Ho.d_in, Ho.width, Ho.depth, Ho.m, Ho.act, Ho.model, Ho.in_scale,
+                      Ho.in_shift, Ho.dom_lo, Ho.dom_hi, Wf, bf, dict(Ho.meta))
+    path = str(tmp_path / "flat_head.sl7w")
+    oracle.save_mlp(flat, path)
+    H2 = S.Mlp.load(path)
+    pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 4, 5, 1000, K=1.0)
+    for prec in ("f32", "f64"):
+        with pytest.raises(L.Sl7Error, match="not distinct"):
+            S.simulate_cdc(pr, H2, prec=prec, seed=1)
+    # the library stays usable
+    H = S.Mlp.load(GBM_WEIGHTS)
+    st, _ = S.simulate_cdc(pr, H, prec="f32", seed=1)
+    assert np.isfinite(st["mean"][0])
