@@ -582,6 +582,7 @@ void fill_inst(const sl7_problem& pr, const Mlp* H, const double* x, InstDev& I)
       s += (double)H->W(0, o, k) * (H->d.in_scale[k] * in[k] + H->d.in_shift[k]);
     I.c0d[o] = s;
     I.c0[o] = (float)s;
+    I.c0lo[o] = (float)(s - (double)I.c0[o]);
   }
 }
 

@@ -101,6 +101,19 @@ __device__ __forceinline__ void first_layer(const f32x4* __restrict__ L, int lan
   }
 }
 
+// The same with c_0 carried as c0 + c0lo, summed in the order of the FP32
+// simulation kernel: (Y w_Y + c0lo) + c0.
+__device__ __forceinline__ void first_layer_split(const f32x4* __restrict__ L, int lane, int sWy,
+                                                  int sC0, int sC0L, float Y, f32x4 z[4]) {
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const f32x4 w = L[(sWy + b) * 64 + lane], c = L[(sC0 + b) * 64 + lane],
+                cl = L[(sC0L + b) * 64 + lane];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) z[b][r] = fmaf(Y, w[r], cl[r]) + c[r];
+  }
+}
+
 // The cotangent d of the first layer's pre-activation against its weights:
 // returns the lane's partial sum of d/dY (16 units), th[k] that of
 // d/dtheta_k.
@@ -135,7 +148,7 @@ __device__ __forceinline__ float first_layer_vjp(const f32x4* __restrict__ L, in
 // block q of the previous tile.
 // ------------------------------------------------------------------------
 struct AmF32 {
-  static constexpr int kWy = kAmWy, kWth = kAmWth, kC0 = kAmC0, kSlots = kAmSlots;
+  static constexpr int kWy = kAmWy, kWth = kAmWth, kC0 = kAmC0, kC0L = kAmC0L, kSlots = kAmSlots;
 
   // Forward evaluation at Y for the wave's 16 paths, in the arithmetic of
   // the simulation kernel's FP32 chain (same products in the same order).
@@ -146,7 +159,7 @@ struct AmF32 {
   static __device__ __forceinline__ f32x4 forward(const f32x4* __restrict__ L, int lane, float Y,
                                                   uint32_t& m01, uint32_t& m23, f32x4 (*der)[4]) {
     f32x4 z[4], Bv[4];
-    first_layer(L, lane, kWy, kC0, Y, z);
+    first_layer_split(L, lane, kWy, kC0, kC0L, Y, z);
     uint32_t mk[4];
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
@@ -239,7 +252,9 @@ struct AmF32 {
 // (activations) or with its sign (cotangents).
 // ------------------------------------------------------------------------
 struct AmX3 {
-  static constexpr int kWy = kXWy, kWth = kXWth, kC0 = kXC0, kSlots = kXSlots;
+  // kC0L < 0: the constant enters once, rounded to FP32; the split operands
+  // round the activations far more coarsely.
+  static constexpr int kWy = kXWy, kWth = kXWth, kC0 = kXC0, kC0L = -1, kSlots = kXSlots;
 
   static __device__ __forceinline__ u32x4 w(const f32x4* L, int slot, int lane) {
     return __builtin_bit_cast(u32x4, L[slot * 64 + lane]);
@@ -553,6 +568,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_adjoint_mfma(AdjArgs a, const u3
   for (int i = threadIdx.x; i < 4 * 64; i += blockDim.x) {
     const int b = i >> 6, g = (i & 63) >> 4;
     L[Net::kC0 * 64 + i] = *(const f32x4*)(I.c0 + 16 * b + 4 * g);
+    if constexpr (Net::kC0L >= 0) L[Net::kC0L * 64 + i] = *(const f32x4*)(I.c0lo + 16 * b + 4 * g);
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;

@@ -327,9 +327,9 @@ __device__ __forceinline__ f32x4 chain_f(const NetRegsF& R, f32x4 Bv[4]) {
   return y;
 }
 
-// One 64-path block: four groups of 16 paths, each for all M steps.  Lane
-// (g = t, n) keeps Y_T of path 16 t + n, so afterwards lane l holds path l of
-// the block, the layout of the fixed-order block reduction.
+// One 64-path block (FP32 network): four groups of 16 paths, each for all M
+// steps.  Lane (g = t, n) keeps Y_T of path 16 t + n, so afterwards lane l
+// holds path l of the block, the layout of the fixed-order block reduction.
 template <class Net>
 __device__ __forceinline__ void sim_block(const SimArgs& a, const InstDev& I, int64_t blk,
                                           const Net& net, const float xr[4], const float lr[4],
@@ -338,9 +338,12 @@ __device__ __forceinline__ void sim_block(const SimArgs& a, const InstDev& I, in
   const uint32_t tag = (uint32_t)I.tag;
   const bool clamp = I.clamp_zero != 0;
   const float dlo = I.dom_lo_f, dhi = I.dom_hi_f;
-  f32x4 c0[4];
+  f32x4 c0[4], c0l[4];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) c0[b] = *(const f32x4*)(I.c0 + 16 * b + 4 * g);
+  for (int b = 0; b < 4; ++b) {
+    c0[b] = *(const f32x4*)(I.c0 + 16 * b + 4 * g);
+    c0l[b] = *(const f32x4*)(I.c0lo + 16 * b + 4 * g);
+  }
   float Yrec = 0.f;
   long long clamped = 0, ood = 0;
   for (int t = 0; t < 4; ++t) {
@@ -358,7 +361,7 @@ __device__ __forceinline__ void sim_block(const SimArgs& a, const InstDev& I, in
         if (i0 + u < M) {
           const float X = __shfl(xc[u], src);
           if (g == t && (Y < dlo || Y > dhi)) ++ood;
-          const f32x4 yv = net.eval(Y, c0);
+          const f32x4 yv = net.eval(Y, c0, c0l);
           Y = interp_rows(X, yv, xr, lr);
           if (clamp && Y < 0.f) {
             Y = 0.f;
@@ -377,9 +380,9 @@ __device__ __forceinline__ void sim_block(const SimArgs& a, const InstDev& I, in
   block_partial(f0, f1, valid ? clamped : 0, valid ? ood : 0, a.partials + I.part_offset + blk);
 }
 
-// The same block with two groups of 16 paths advanced together (groups t and
-// t + 1, t = 0, 2), their networks evaluated by Net::eval_pair.  Every path
-// takes exactly the arithmetic of sim_block, so the results are identical.
+// The same block for the 16-bit networks, with two groups of 16 paths
+// advanced together (groups t and t + 1, t = 0, 2), their networks evaluated
+// by Net::eval_pair; each path's arithmetic does not depend on its partner.
 // The first-layer constants of the block's instance sit in the lane's own
 // LDS slots c0s[64 b + lane] (written and read only by that lane), which
 // leaves their registers to the second group.
@@ -446,16 +449,6 @@ __device__ __forceinline__ void sim_block_pair(const SimArgs& a, const InstDev& 
 template <int P, int ACT>
 struct NetH {
   NetRegsH<P> R;
-  __device__ __forceinline__ f32x4 eval(float Y, const f32x4 c0[4]) const {
-    f32x4 z[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const f32x4 w = R.C.wy(b, R.lane);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) z[b][r] = fmaf(Y, w[r], c0[b][r]);
-    }
-    return chain_h<P, ACT>(R, pack8<P, ACT>(z[0], z[1]), pack8<P, ACT>(z[2], z[3]));
-  }
   __device__ __forceinline__ f32x4 eval_z0(const f32x4 z[4]) const {
     return chain_h<P, ACT>(R, pack8<P, ACT>(z[0], z[1]), pack8<P, ACT>(z[2], z[3]));
   }
@@ -482,12 +475,17 @@ struct NetH {
 template <int ACT>
 struct NetF {
   NetRegsF R;
-  __device__ __forceinline__ f32x4 eval(float Y, const f32x4 c0[4]) const {
+  // First layer Y wY + c0, with c0 carried as c0h + c0l (the FP64 constant
+  // to about 2^-48): c0l joins the product before c0h, so the rounding of
+  // c0 to FP32, the same for every path and step, does not enter; only the
+  // rounding of the sum does.
+  __device__ __forceinline__ f32x4 eval(float Y, const f32x4 c0h[4], const f32x4 c0l[4]) const {
     f32x4 Bv[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Bv[b][r] = act_f<ACT>(fmaf(Y, R.wY[b][r], c0[b][r]));
+      for (int r = 0; r < 4; ++r)
+        Bv[b][r] = act_f<ACT>(fmaf(Y, R.wY[b][r], c0l[b][r]) + c0h[b][r]);
     return chain_f<ACT>(R, Bv);
   }
   __device__ __forceinline__ f32x4 eval_z0(const f32x4 z[4]) const {
@@ -501,16 +499,6 @@ struct NetF {
 template <int P, int ACT>
 struct NetX3 {
   NetRegsX3<P> R;
-  __device__ __forceinline__ f32x4 eval(float Y, const f32x4 c0[4]) const {
-    f32x4 z[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const f32x4 w = R.C.wy(b, R.lane);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) z[b][r] = fmaf(Y, w[r], c0[b][r]);
-    }
-    return chain_x3<P, ACT>(R, z);
-  }
   __device__ __forceinline__ f32x4 eval_z0(const f32x4 z[4]) const { return chain_x3<P, ACT>(R, z); }
   static constexpr bool kPair = true;
   __device__ __forceinline__ void eval_pair(float Ya, float Yb, const f32x4* c0, f32x4& ya,

@@ -47,7 +47,8 @@ hipError_t launch_adjoint_mfma(int prec, int act, const AdjArgs& a, const void* 
 
 // Slots of the MFMA sweep's LDS image (one 16-byte slot per lane, 64 lanes
 // per slot).  The host fills slots [0, kAmC0); the kernel fills the
-// instance's first-layer constant.  Lane (g, i) = (lane / 16, lane % 16);
+// instance's first-layer constant (in FP32 as c0 + c0lo, the FP32 rounding
+// of the FP64 constant and the rest).  Lane (g, i) = (lane / 16, lane % 16);
 // element e of a slot.
 //   kAmFwd   + 16 l + 4 b + q : W_{l+1}[16 b + i][16 q + 4 g + e]
 //   kAmHead  + q              : W_head[i][16 q + 4 g + e]          (i < m)
@@ -57,9 +58,10 @@ hipError_t launch_adjoint_mfma(int prec, int act, const AdjArgs& a, const void* 
 //   kAmRevH  + b              : W_head[4 g + e][16 b + i]          (4 g + e < m)
 //   kAmWth   + 4 k + b        : W_0[16 b + 4 g + e][theta_k] x its input scale
 //   kAmC0    + b              : first-layer constant (bias, dt and theta folded)
+//   kAmC0L   + b              : its rest c0lo
 constexpr int kAmFwd = 0, kAmHead = 48, kAmBias = 52, kAmWy = 65, kAmRev = 69, kAmRevH = 117,
-              kAmWth = 121, kAmC0 = 133, kAmSlots = 137;
-static_assert(kAmWy + 4 == kAmRev && kAmWth + 12 == kAmC0, "slot map");
+              kAmWth = 121, kAmC0 = 133, kAmC0L = 137, kAmSlots = 141;
+static_assert(kAmWy + 4 == kAmRev && kAmWth + 12 == kAmC0 && kAmC0 + 4 == kAmC0L, "slot map");
 
 // The BF16X3 image: 16-byte slots of eight BF16 values (weights, as hi =
 // rn(w) and lo = rn(w - hi) in two copies of each layout) or four floats.

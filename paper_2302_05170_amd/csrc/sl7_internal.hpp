@@ -38,6 +38,8 @@ struct alignas(16) InstDev {
   double K, Y0, dt, dom_lo, dom_hi;
   double A[kMaxM], B[kMaxM];  // analytic map: y_j = A_j * Y + B_j
   alignas(16) float c0[kWidth]; // network: first-layer constant (dt, theta folded)
+  alignas(16) float c0lo[kWidth];  // c0d - c0 rounded: the FP32 kernels add Y wY + c0lo
+                                   // before c0, so the constant enters at FP64 accuracy
   double c0d[kWidth];         // the same in FP64
 };
 
@@ -117,6 +119,7 @@ hipError_t launch_eval_lane(const double* net, const double* w0full, int d_in, i
 
 namespace sl7 {
 static_assert(offsetof(InstDev, c0) % 16 == 0, "c0 is read with 16-byte loads");
+static_assert(offsetof(InstDev, c0lo) % 16 == 0, "c0lo is read with 16-byte loads");
 static_assert(sizeof(Partial) == 64, "partial layout");
 static_assert(offsetof(Partial, s) == 0 && offsetof(Partial, q) == 16 &&
                   offsetof(Partial, clamped) == 32 && offsetof(Partial, ood) == 40,

@@ -205,3 +205,30 @@ def test_split_mode_needs_a_network(S):
     pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 4, 5, 100, K=1.0)
     with pytest.raises(L.Sl7Error, match="needs a network"):
         S.adjoint(pr, None, prec="bf16x3", seed=1)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_reverse_sweep_only_for_paths_with_nonzero_payoff_derivative(S, prec):
+    """The reverse sweep visits only paths with f'(Y_T) != 0.  A strike above
+    every Y_T leaves none: value and sensitivities exactly zero, per path
+    too.  A strike below every Y_T makes every path active: the call's
+    sensitivities then equal those of Y_T itself, path by path and bit for
+    bit, and its value is E[Y_T] - K."""
+    H = S.Mlp.load(GBM_WEIGHTS)
+    base = dict(model=W.GBM, theta=(0.3, 0.1), Y0=1.0, T=1.0, M=16, m=5, N=3000)
+    pr0 = S.Problem(base["model"], base["theta"], base["Y0"], base["T"], base["M"], base["m"],
+                    base["N"], K=1.0)
+    g0, p0 = S.adjoint(pr0, H, prec=prec, seed=5, payoff=0, ckpt_every=4, per_path=True)
+    p0 = p0.cpu().numpy()
+    lo, hi = p0[:, 0].min(), p0[:, 0].max()
+    prh = S.Problem(base["model"], base["theta"], base["Y0"], base["T"], base["M"], base["m"],
+                    base["N"], K=2 * hi)
+    gh, ph = S.adjoint(prh, H, prec=prec, seed=5, payoff=1, ckpt_every=4, per_path=True)
+    assert gh["value"] == 0.0 and all(v == 0.0 for v in gh["grad"])
+    assert not np.any(ph.cpu().numpy())
+    prl = S.Problem(base["model"], base["theta"], base["Y0"], base["T"], base["M"], base["m"],
+                    base["N"], K=0.5 * lo)
+    gl, pl = S.adjoint(prl, H, prec=prec, seed=5, payoff=1, ckpt_every=4, per_path=True)
+    pl = pl.cpu().numpy()
+    assert np.array_equal(pl[:, 1:], p0[:, 1:])
+    assert np.allclose(pl[:, 0], p0[:, 0] - np.float64(np.float32(0.5 * lo)), rtol=0, atol=1e-15)

@@ -128,34 +128,56 @@ def cir_oracle_paths(S):
     return prs, ref
 
 
-def test_batched_launch_means_match_oracle(S, H, cir_oracle_paths):
+@pytest.fixture(scope="module")
+def cir_oracle_means(cir_oracle_paths):
+    """The oracle's two payoff means (Y_T and max(Y_T - ybar, 0)) of every
+    one of the 256 instances at its full path count (the spanning instances'
+    from their stored paths)."""
+    prs, ref = cir_oracle_paths
+    Ho = oracle.load_mlp(CIR_WEIGHTS)
+    means = {}
+    for k, pr in enumerate(prs):
+        if k in ref:
+            y = ref[k][0]
+        else:
+            opr = oracle.Problem(pr.model, pr.theta, pr.Y0, pr.T, pr.M, pr.m, pr.instance)
+            y = oracle.simulate(opr, Ho, 11, np.arange(pr.N))[0]
+        means[k] = [oracle.estimate(f)["mean"] for f in oracle.payoffs(y, pr.K)]
+    return prs, means
+
+
+def test_batched_launch_means_match_oracle(S, H, cir_oracle_means):
     """The whole 256-instance batch in one persistent FP32 launch replayed
-    from its graph: each spanning instance's two payoff means (Y_T and
+    from its graph: every instance's two payoff means (Y_T and
     max(Y_T - ybar, 0)) against the oracle's means over the same paths, at
     1e-6 relative to max(|mean|, ybar).  The call's mean can be a few
     thousandths, where 1e-6 of it is below the FP32 spacing of Y near ybar;
-    ybar is the same floor as for the per-path errors.  The plain relative
-    error is printed."""
-    prs, ref = cir_oracle_paths
-    assert len(ref) >= 64
-    assert min(prs[k].M for k in ref) == 4 and max(prs[k].M for k in ref) == 32
+    ybar is the same floor as for the per-path errors.  The FP32 kernel
+    carries the first-layer constant as two floats: rounded once to FP32 it
+    would shift every path of an instance alike, by up to 8e-7 of ybar in
+    the mean on this workload.  The plain relative error is printed."""
+    prs, means = cir_oracle_means
+    assert len(means) == 256
     got = S.simulate_batched(prs, H, prec="f32", seed=11, use_graph=True)
     worst = [0.0, 0.0]
     plain = [(0.0, -1, 0.0)] * 2
-    for k, (y, ncl, nood, _) in ref.items():
+    miss = []
+    for k, mk in means.items():
         assert got[k]["n"] == prs[k].N
-        for j, f in enumerate(oracle.payoffs(y, prs[k].K)):
-            e = oracle.estimate(f)
-            diff = abs(got[k]["mean"][j] - e["mean"])
-            d = diff / max(abs(e["mean"]), prs[k].theta[1])
+        for j in range(2):
+            diff = abs(got[k]["mean"][j] - mk[j])
+            d = diff / max(abs(mk[j]), prs[k].theta[1])
             worst[j] = max(worst[j], d)
-            if diff / abs(e["mean"]) > plain[j][0]:
-                plain[j] = (diff / abs(e["mean"]), k, e["mean"])
-            assert d <= 1e-6, (k, j, d)
-    print(f"batched f32 over {len(ref)} instances at full N: max error of the means "
+            rel = diff / max(abs(mk[j]), 1e-300)
+            if rel > plain[j][0]:
+                plain[j] = (rel, k, mk[j])
+            if d > 1e-6:
+                miss.append((k, j, d))
+    print(f"batched f32 over {len(means)} instances at full N: max error of the means "
           f"{worst[0]:.2e} (Y_T), {worst[1]:.2e} (call) against max(|mean|, ybar); plain "
           f"relative {plain[0][0]:.2e} (instance {plain[0][1]}, mean {plain[0][2]:.3e}), "
           f"{plain[1][0]:.2e} (instance {plain[1][1]}, mean {plain[1][2]:.3e})")
+    assert not miss, miss
 
 
 # Absolute term per step for CIR.  The CIR network's inputs are scaled to
