@@ -10,13 +10,13 @@ against sanity bounds, 0.5 / 0.1, twice the worst error measured on this
 network: the weights rounded once make a fixed bias in every step, which the
 tail paths below amplify).
 
-FP32: 1e-5 for every path whose normals stay within |X| <= 4; a path that
-draws a larger |X| extrapolates the degree-4 interpolant there, which
-multiplies the network's FP32 output error (rms 2.2e-7 measured on this
-network) by the Lebesgue function (22.6 at |X| = 4, 43 at 4.5, 89 at 5.2), and
-is held to 1e-5 scaled by that function (tests/lebesgue.py).  A plain FP32
-evaluation of this network and interpolant on the CPU, with rounded products
-and sequential FP32 sums, reaches the same size of error on such paths.
+FP32: 1e-5 for every path.  A path that draws some |X| > 4 extrapolates the
+degree-4 interpolant there, which multiplies the network's FP32 output error
+by the Lebesgue function (22.6 at |X| = 4, 43 at 4.5, 89 at 5.2); those
+paths (97 of the 2e5) stay within the gate because the kernel carries the
+first-layer constant as two floats.  Rounded once to FP32, that constant
+shifted every output of a step alike, and the extrapolating paths reached
+1.26e-5.  Errors are printed separately for paths with all |X| <= 4.
 """
 import os
 
@@ -26,7 +26,6 @@ import torch
 
 import oracle
 import workloads as W
-from lebesgue import f32_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -99,9 +98,7 @@ def test_table61_path_counts(S, H, ref_paths, prec):
               f"{e[inner].max():.3e}; {np.count_nonzero(~inner)} extrapolating paths: "
               f"{e[~inner].max() if np.any(~inner) else 0.0:.3e}")
         assert st["n"] == N
-        assert e[inner].max() <= TOL[prec], (prec, N, e[inner].max())
-        bound = f32_bound(PAPER["m"], xmax_all[:N]) if prec == "f32" else TOL[prec]
-        assert np.all(e <= bound), (prec, N, e.max(), (e / bound).max())
+        assert e.max() <= TOL[prec], (prec, N, e.max())
         if prec in ("f64", "f32"):
             f = oracle.estimate(ref_all[:N])
             assert abs(st["mean"][0] - f["mean"]) <= (1e-12 if prec == "f64" else 1e-6) * max(
