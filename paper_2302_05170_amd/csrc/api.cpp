@@ -461,14 +461,19 @@ int Mlp::ensure_device(int prec) {
   rc = upload(*pack[prec], pk.data(), pk.size() * sizeof(uint32_t));
   if (rc) { pack[prec].reset(); return rc; }
   if (!w0n) {
-    std::vector<float> a(64 * d.d_in), c(64);
+    // each value as its FP32 rounding followed by the FP32 rounding of the
+    // rest: [64 x d_in] hi then lo, [64] hi then lo
+    std::vector<float> a(2 * 64 * d.d_in), c(2 * 64);
     for (int o = 0; o < 64; ++o) {
       double s = b(0, o);
       for (int k = 0; k < d.d_in; ++k) {
-        a[o * d.d_in + k] = (float)((double)W(0, o, k) * d.in_scale[k]);
+        const double v = (double)W(0, o, k) * d.in_scale[k];
+        a[o * d.d_in + k] = (float)v;
+        a[64 * d.d_in + o * d.d_in + k] = (float)(v - (double)a[o * d.d_in + k]);
         s += (double)W(0, o, k) * d.in_shift[k];
       }
       c[o] = (float)s;
+      c[64 + o] = (float)(s - (double)c[o]);
     }
     w0n.reset(new DevBuf());
     c0n.reset(new DevBuf());

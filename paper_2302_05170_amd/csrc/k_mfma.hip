@@ -589,8 +589,9 @@ hipError_t launch_sim_mfma(int prec, int act, const SimArgs& a, int grid, int wa
 // ------------------------------------------------------------------------
 // Batched network evaluation (eq. 6.4) on the same MFMA chain: 16 rows per
 // wave pass; the first layer is a full d_in-wide product in FP32.
-// w0n: [64 x d_in] first-layer weights times input scales; c0n: [64] the
-// shift and bias folded.
+// w0n: [64 x d_in] first-layer weights times input scales, then [64 x d_in]
+// their FP32 rests (each value less its FP32 rounding); c0n: [64] the shift
+// and bias folded, then [64] their rests.
 // ------------------------------------------------------------------------
 template <class Net>
 __device__ __forceinline__ void eval_rows(const Net& net, const float* __restrict__ w0n,
@@ -612,11 +613,15 @@ __device__ __forceinline__ void eval_rows(const Net& net, const float* __restric
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int o = 16 * b + 4 * g + r;
-        float s = c0n[o];
+        // the small parts first, then the FP32 roundings of the constants
+        float s = c0n[64 + o];
+#pragma unroll
+        for (int k = 0; k < kMaxDinLane; ++k)
+          if (k < d_in) s = fmaf(w0n[64 * d_in + o * d_in + k], x[k], s);
 #pragma unroll
         for (int k = 0; k < kMaxDinLane; ++k)
           if (k < d_in) s = fmaf(w0n[o * d_in + k], x[k], s);
-        z[b][r] = s;
+        z[b][r] = s + c0n[o];
       }
     const f32x4 y = net.eval_z0(z);
 #pragma unroll
