@@ -194,13 +194,15 @@ struct AmF32 {
     }
     f32x4 y = (f32x4){0.f, 0.f, 0.f, 0.f};
     if constexpr (HEAD) {
-      y = L[(kAmBias + 12) * 64 + lane];
+      // four accumulators summed pairwise, as in the simulation kernel
+      f32x4 ya[4] = {L[(kAmBias + 12) * 64 + lane], y, y, y};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const f32x4 A = L[(kAmHead + q) * 64 + lane];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) y = mfma4(A[e], Bv[q][e], y);
+        for (int e = 0; e < 4; ++e) ya[e] = mfma4(A[e], Bv[q][e], ya[e]);
       }
+      y = (ya[0] + ya[1]) + (ya[2] + ya[3]);
     }
     return y;
   }

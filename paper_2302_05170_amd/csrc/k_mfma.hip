@@ -320,11 +320,18 @@ __device__ __forceinline__ f32x4 chain_f(const NetRegsF& R, f32x4 Bv[4]) {
 #pragma unroll
     for (int b = 0; b < 4; ++b) Bv[b] = act4<ACT>(acc[b]);
   }
-  f32x4 y = R.C.head(R.lane);
+  // The head's 64 products go to four accumulators (K block 4 q + e into
+  // accumulator e), summed pairwise at the end: the collocation values are
+  // small sums of larger terms of both signs, and one 64-term FP32 chain
+  // roughly doubles their rounding error, which an extrapolating
+  // interpolant then multiplies.
+  f32x4 y[4] = {R.C.head(R.lane), (f32x4){0.f, 0.f, 0.f, 0.f}, (f32x4){0.f, 0.f, 0.f, 0.f},
+                (f32x4){0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
   for (int kb = 0; kb < 16; ++kb)
-    y = __builtin_amdgcn_mfma_f32_16x16x4f32(R.Ah[kb], Bv[kb >> 2][kb & 3], y, 0, 0, 0);
-  return y;
+    y[kb & 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(R.Ah[kb], Bv[kb >> 2][kb & 3], y[kb & 3], 0,
+                                                     0, 0);
+  return (y[0] + y[1]) + (y[2] + y[3]);
 }
 
 // One 64-path block (FP32 network): four groups of 16 paths, each for all M
