@@ -149,6 +149,11 @@ __device__ __forceinline__ float first_layer_vjp(const f32x4* __restrict__ L, in
 // ------------------------------------------------------------------------
 struct AmF32 {
   static constexpr int kWy = kAmWy, kWth = kAmWth, kC0 = kAmC0, kC0L = kAmC0L, kSlots = kAmSlots;
+  static constexpr bool kPairFwd = false;
+  template <int ACT>
+  static __device__ __forceinline__ void forward_pair(const f32x4*, int, float, float,
+                                                      uint32_t (&)[2], uint32_t (&)[2], f32x4&,
+                                                      f32x4&) {}
 
   // Forward evaluation at Y for the wave's 16 paths, in the arithmetic of
   // the simulation kernel's FP32 chain (same products in the same order).
@@ -310,6 +315,67 @@ struct AmX3 {
     return y;
   }
 
+  // The forward evaluation of two groups at once (HEAD, no derivatives): the
+  // same arithmetic as forward for each, with every weight slot read from
+  // LDS once for both groups' products.
+  template <int ACT>
+  static __device__ __forceinline__ void forward_pair(const f32x4* __restrict__ L, int lane,
+                                                      float Ya, float Yb, uint32_t (&ma)[2],
+                                                      uint32_t (&mb)[2], f32x4& ya, f32x4& yb) {
+    f32x4 za[4], zb[4];
+    first_layer(L, lane, kWy, kC0, Ya, za);
+    first_layer(L, lane, kWy, kC0, Yb, zb);
+    ma[0] = ma[1] = mb[0] = mb[1] = 0u;
+    bf16x8 ha0, ha1, la0, la1, hb0, hb1, lb0, lb1;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      if constexpr (ACT == SL7_RELU) {
+        ma[l >> 1] |= tile_mask(za) << (16 * (l & 1));
+        mb[l >> 1] |= tile_mask(zb) << (16 * (l & 1));
+      }
+      split8<SL7_BF16X3, ACT>(za[0], za[1], ha0, la0);
+      split8<SL7_BF16X3, ACT>(za[2], za[3], ha1, la1);
+      split8<SL7_BF16X3, ACT>(zb[0], zb[1], hb0, lb0);
+      split8<SL7_BF16X3, ACT>(zb[2], zb[3], hb1, lb1);
+      if (l == 3) break;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int s = 8 * l + 2 * b;
+        const f32x4 bias = L[(kXBias + 4 * l + b) * 64 + lane];
+        const u32x4 wl0 = w(L, kXFwdL + s, lane), wl1 = w(L, kXFwdL + s + 1, lane);
+        const u32x4 wh0 = w(L, kXFwdH + s, lane), wh1 = w(L, kXFwdH + s + 1, lane);
+        f32x4 acc = mfma32(wl0, ha0, bias);
+        acc = mfma32(wl1, ha1, acc);
+        acc = mfma32(wh0, la0, acc);
+        acc = mfma32(wh1, la1, acc);
+        acc = mfma32(wh0, ha0, acc);
+        za[b] = mfma32(wh1, ha1, acc);
+        f32x4 acb = mfma32(wl0, hb0, bias);
+        acb = mfma32(wl1, hb1, acb);
+        acb = mfma32(wh0, lb0, acb);
+        acb = mfma32(wh1, lb1, acb);
+        acb = mfma32(wh0, hb0, acb);
+        zb[b] = mfma32(wh1, hb1, acb);
+      }
+    }
+    const f32x4 bias = L[(kXBias + 12) * 64 + lane];
+    const u32x4 wl0 = w(L, kXFwdL + 24, lane), wl1 = w(L, kXFwdL + 25, lane);
+    const u32x4 wh0 = w(L, kXFwdH + 24, lane), wh1 = w(L, kXFwdH + 25, lane);
+    ya = mfma32(wl0, ha0, bias);
+    ya = mfma32(wl1, ha1, ya);
+    ya = mfma32(wh0, la0, ya);
+    ya = mfma32(wh1, la1, ya);
+    ya = mfma32(wh0, ha0, ya);
+    ya = mfma32(wh1, ha1, ya);
+    yb = mfma32(wl0, hb0, bias);
+    yb = mfma32(wl1, hb1, yb);
+    yb = mfma32(wh0, lb0, yb);
+    yb = mfma32(wh1, lb1, yb);
+    yb = mfma32(wh0, hb0, yb);
+    yb = mfma32(wh1, hb1, yb);
+  }
+  static constexpr bool kPairFwd = true;
+
   template <int ACT>
   static __device__ __forceinline__ float reverse(const f32x4* __restrict__ L, int lane,
                                                   f32x4 ybar, uint32_t m01, uint32_t m23,
@@ -394,6 +460,28 @@ __device__ __forceinline__ float am_step(const f32x4* L, int lane, float Y, floa
   return Yn;
 }
 
+// Two groups' forward steps at once (Net::forward_pair), each exactly as
+// am_step.
+template <class Net, int ACT, bool STORE>
+__device__ __forceinline__ void am_step_pair(const f32x4* L, int lane, float& Ya, float& Yb,
+                                             float Xa, float Xb, const float xr[4],
+                                             const float lr[4], bool clamp, u32x4* sta,
+                                             u32x4* stb) {
+  uint32_t ma[2] = {0u, 0u}, mb[2] = {0u, 0u};
+  f32x4 ya, yb;
+  Net::template forward_pair<ACT>(L, lane, Ya, Yb, ma, mb, ya, yb);
+  float Yna = interp_rows(Xa, ya, xr, lr), Ynb = interp_rows(Xb, yb, xr, lr);
+  const bool cla = clamp && Yna < 0.f, clb = clamp && Ynb < 0.f;
+  if (cla) Yna = 0.f;
+  if (clb) Ynb = 0.f;
+  if constexpr (STORE) {
+    *sta = (u32x4){ma[0], ma[1], f2u(Ya), cla ? 1u : 0u};
+    *stb = (u32x4){mb[0], mb[1], f2u(Yb), clb ? 1u : 0u};
+  }
+  Ya = Yna;
+  Yb = Ynb;
+}
+
 // Lanes below the calling lane whose bit is set in the wave mask m.
 __device__ __forceinline__ int lanes_below(uint64_t m) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
@@ -444,6 +532,37 @@ __device__ __forceinline__ void am_block(const AdjArgs& a, const InstDev& I, con
   // forward pass of the four groups; lane l keeps f and the activity of path l
   double f_own = 0.0;
   bool act_own = false;
+  if constexpr (Net::kPairFwd) {
+    // two groups at a time, sharing the weight reads
+    for (int t = 0; t < 4; t += 2) {
+      if (base + 16 * t >= N) break;
+      const int64_t pa = base + 16 * t + n, pb = pa + 16;
+      const bool va = pa < N, vb = pb < N;
+      StepNormals nra, nrb;
+      float Ya = I.Y0_f, Yb = I.Y0_f;
+      for (int i = 0; i < M; ++i) {
+        if (i % k == 0) {
+          if (va) ck[(int64_t)(i / k) * N + pa] = Ya;
+          if (vb) ck[(int64_t)(i / k) * N + pb] = Yb;
+        }
+        const float Xa = nra.get(a, i, I.path_offset + pa, tag, g, n);
+        const float Xb = nrb.get(a, i, I.path_offset + pb, tag, g, n);
+        if (i >= ib_keep)
+          am_step_pair<Net, ACT, true>(L, lane, Ya, Yb, Xa, Xb, xr, lr, clamp,
+                                       slot(t, i, lane), slot(t + 1, i, lane));
+        else
+          am_step_pair<Net, ACT, false>(L, lane, Ya, Yb, Xa, Xb, xr, lr, clamp, nullptr, nullptr);
+      }
+      if (g == t && va) {
+        f_own = a.payoff == 0 ? (double)Ya : fmax((double)Ya - (double)K, 0.0);
+        act_own = a.payoff == 0 || Ya > K;
+      }
+      if (g == t + 1 && vb) {
+        f_own = a.payoff == 0 ? (double)Yb : fmax((double)Yb - (double)K, 0.0);
+        act_own = a.payoff == 0 || Yb > K;
+      }
+    }
+  } else
   for (int t = 0; t < 4; ++t) {
     if (base + 16 * t >= N) break;
     const int64_t p = base + 16 * t + n;
