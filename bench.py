@@ -46,7 +46,7 @@ ISSUED = {"bf16": 2 * (3 * 64 * 64 + 64 * 16), "f16": 2 * (3 * 64 * 64 + 64 * 16
 ISSUED["bf16x3"] = ISSUED["f16x3"] = 3 * ISSUED["bf16"]
 
 
-PROFILE_X3 = os.path.join(ROOT, "profiles", "k_sim_mfma_x3_bf16x3_gbm_N2e24_M32.md")
+PROFILE_X3 = os.path.join(ROOT, "profiles", "k_sim_mfma_x3l_bf16x3_gbm_N2e24_M32.md")
 
 
 def profiled(field, path=PROFILE_X3):

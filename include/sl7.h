@@ -147,7 +147,10 @@ typedef struct {
 
 /* Launch plan of the fused kernel.  A plan changes speed, never results. */
 typedef struct {
-  int32_t waves_per_block; /* 1, 2 or 4 wave64s per workgroup */
+  int32_t waves_per_block; /* 1, 2 or 4 wave64s per workgroup; also 12 in the split
+                              modes SL7_BF16X3 / SL7_F16X3 (all weights in LDS, three
+                              waves per SIMD; the default there from 64 blocks of
+                              64 paths per compute unit) */
   int32_t blocks_per_cu;   /* persistent grid = blocks_per_cu x compute units */
   int32_t grab;            /* 64-path blocks taken per work-queue grab */
   int32_t reserved;

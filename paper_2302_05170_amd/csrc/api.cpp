@@ -613,7 +613,13 @@ int fill_nodes(int m, SimArgs& a, double* x_out) {
   return SL7_OK;
 }
 
-int default_plan(int prec, sl7_plan* p) {
+int64_t total_blocks(const sl7_problem* prs, int n) {
+  int64_t b = 0;
+  for (int k = 0; k < n; ++k) b += (prs[k].N + 63) / 64;
+  return b;
+}
+
+int default_plan(int prec, int64_t n_blocks, int n_cu, sl7_plan* p) {
   p->waves_per_block = 4;
   // register-limited occupancy of the MFMA kernels; the lane kernels of the
   // piecewise-linear form hide their table loads with more waves
@@ -622,13 +628,23 @@ int default_plan(int prec, sl7_plan* p) {
   // atomic (measured 5 % faster than one)
   p->grab = is_pwl(prec) ? 4 : 1;
   p->reserved = 0;
+  // the split modes' all-LDS kernel (three waves per SIMD) once every wave
+  // of the chip has several 64-path blocks to run; with fewer, each
+  // product's LDS read is exposed and the register kernel is faster
+  if (is_x3(prec) && n_cu > 0 && n_blocks >= (int64_t)kX3LBlocksPerCu * n_cu) {
+    p->waves_per_block = kWavesX3L;
+    p->blocks_per_cu = 1;
+  }
   return SL7_OK;
 }
 
-int check_plan(const sl7_plan* p) {
-  // the fused kernels are compiled for at most 256 threads per workgroup
-  if (p->waves_per_block != 1 && p->waves_per_block != 2 && p->waves_per_block != 4)
-    return fail(SL7_EINVAL, "plan.waves_per_block=%d not in {1,2,4}", p->waves_per_block);
+int check_plan(const sl7_plan* p, int prec) {
+  // the fused kernels are compiled for at most 256 threads per workgroup,
+  // the split modes' all-LDS kernel for 768
+  const int w = p->waves_per_block;
+  if (w != 1 && w != 2 && w != 4 && !(is_x3(prec) && w == kWavesX3L))
+    return fail(SL7_EINVAL, "plan.waves_per_block=%d not in {1,2,4}%s", w,
+                is_x3(prec) ? " or 12" : " (12 only in the split modes)");
   if (p->blocks_per_cu < 1 || p->blocks_per_cu > 64) return fail(SL7_EINVAL, "plan.blocks_per_cu=%d outside [1, 64]", p->blocks_per_cu);
   if (p->grab < 1 || p->grab > 4096) return fail(SL7_EINVAL, "plan.grab=%d outside [1, 4096]", p->grab);
   return SL7_OK;
@@ -753,8 +769,9 @@ int launch_sequence(const SimArgs& a_in, int n, int64_t N0, const Mlp* H, int pr
 int run_instances(const sl7_problem* prs, int n, const Mlp* H, int prec, uint64_t seed,
                   void* YT_dev, const sl7_plan* plan_in, hipStream_t stream, Workspace& ws) {
   sl7_plan plan;
-  if (plan_in) plan = *plan_in; else default_plan(prec, &plan);
-  int rc = check_plan(&plan);
+  if (plan_in) plan = *plan_in;
+  else default_plan(prec, total_blocks(prs, n), ws.n_cu, &plan);
+  int rc = check_plan(&plan, prec);
   if (rc) return rc;
   SimArgs a;
   rc = prepare_instances(prs, n, H, prec, seed, YT_dev, stream, ws, a);
@@ -888,7 +905,7 @@ int sl7_simulate(const sl7_problem* pr, const sl7_mlp* Hc, int prec, uint64_t se
   int rc = check_problem(pr, H, prec, "pr");
   if (rc) return rc;
   if (plan) {
-    rc = check_plan(plan);
+    rc = check_plan(plan, prec);
     if (rc) return rc;
   }
   if (H) {

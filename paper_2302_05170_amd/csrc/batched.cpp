@@ -85,14 +85,15 @@ extern "C" int sl7_simulate_batched(const sl7_problem* prs, int n, const sl7_mlp
   int rc = check_batch(prs, n, H, prec);
   if (rc) return rc;
   if (!stats_host) return fail(SL7_EINVAL, "stats_host is NULL");
-  sl7_plan plan;
-  if (plan_in) plan = *plan_in; else default_plan(prec, &plan);
-  rc = check_plan(&plan);
-  if (rc) return rc;
-  rc = H->ensure_device(prec);
-  if (rc) return rc;
   int dev;
   rc = current_device(&dev);
+  if (rc) return rc;
+  sl7_plan plan;
+  if (plan_in) plan = *plan_in;
+  else default_plan(prec, total_blocks(prs, n), workspace(dev).n_cu, &plan);
+  rc = check_plan(&plan, prec);
+  if (rc) return rc;
+  rc = H->ensure_device(prec);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   std::vector<sl7_problem> p(prs, prs + n);
@@ -196,7 +197,7 @@ std::string plan_key(int prec, const Mlp* H) {
   return b;
 }
 
-bool cache_lookup(const char* path, const std::string& key, sl7_plan* out) {
+bool cache_lookup(const char* path, const std::string& key, int prec, sl7_plan* out) {
   std::ifstream f(path);
   if (!f) return false;
   std::string line;
@@ -214,7 +215,7 @@ bool cache_lookup(const char* path, const std::string& key, sl7_plan* out) {
     p.waves_per_block = atoi(w + 18);
     p.blocks_per_cu = atoi(b + 16);
     p.grab = atoi(g + 7);
-    if (check_plan(&p) == SL7_OK) {
+    if (check_plan(&p, prec) == SL7_OK) {
       *out = p;
       found = true;  // last matching line wins
     }
@@ -232,14 +233,14 @@ namespace {
 int time_candidates(const sl7_problem* prs, int n, Mlp* H, int prec, hipStream_t s, Workspace& ws,
                     sl7_plan* bestp_out, float* best_out) {
   std::vector<sl7_plan> cands(1);
-  default_plan(prec, &cands[0]);
-  const int wpb[] = {1, 2, 4};
+  default_plan(prec, total_blocks(prs, n), ws.n_cu, &cands[0]);
+  const int wpb[] = {1, 2, 4, kWavesX3L};
   const int bpc[] = {1, 2, 3, 4, 8, 16};
   const int grabs[] = {1, 4};
   for (int w : wpb)
     for (int b : bpc)
       for (int g : grabs) {
-        if (w * b > 32) continue;
+        if (w * b > 32 || (w == kWavesX3L && !is_x3(prec))) continue;
         sl7_plan p = {w, b, g, 0};
         if (p.waves_per_block == cands[0].waves_per_block && p.blocks_per_cu == cands[0].blocks_per_cu &&
             p.grab == cands[0].grab)
@@ -298,7 +299,7 @@ extern "C" int sl7_autotune(const sl7_problem* shape, const sl7_mlp* Hc, int pre
   if (rc) return rc;
   if (prec == SL7_F64) return fail(SL7_EUNSUPPORTED, "F64 runs the per-lane kernel (no plan)");
   const std::string key = plan_key(prec, H);
-  if (cache_path && cache_lookup(cache_path, key, out)) return SL7_OK;
+  if (cache_path && cache_lookup(cache_path, key, prec, out)) return SL7_OK;
   rc = H->ensure_device(prec);
   if (rc) return rc;
   int dev;
@@ -336,7 +337,7 @@ extern "C" int sl7_autotune_batched(const sl7_problem* prs, int n, const sl7_mlp
   char hb[40];
   snprintf(hb, sizeof(hb), "/batch%016llx", (unsigned long long)h);
   const std::string key = plan_key(prec, H) + hb;
-  if (cache_path && cache_lookup(cache_path, key, out)) return SL7_OK;
+  if (cache_path && cache_lookup(cache_path, key, prec, out)) return SL7_OK;
   rc = H->ensure_device(prec);
   if (rc) return rc;
   int dev;

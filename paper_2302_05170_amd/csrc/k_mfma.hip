@@ -111,13 +111,16 @@ __device__ __forceinline__ f32x4 chain_h(const NetRegsH<P>& R, typename H16<P>::
   return H16<P>::mfma(R.Ah[1], B1, y);
 }
 
-template <int P>
+// HL: the hi parts in LDS too (a 12-wave workgroup shares one copy and a
+// wave needs at most 168 VGPRs: three waves per SIMD), else in VGPRs.
+template <int P, bool HL = false>
 struct NetRegsX3 {
   typedef typename Split16<P>::v8 v8;
-  v8 A[3][4][2];        // hi parts of the hidden-layer weights
-  v8 Ah[2];             // hi parts of the head weights
-  BiasLds C;            // biases and first-layer weights of Y
-  const u32x4* lo;      // LDS: lo parts, hidden [3][4][2] then head [2], [slot][lane]
+  v8 A[HL ? 1 : 3][4][2];  // hi parts of the hidden-layer weights (VGPRs)
+  v8 Ah[2];                // hi parts of the head weights (VGPRs)
+  BiasLds C;               // biases and first-layer weights of Y
+  const u32x4* lo;         // LDS: lo parts, hidden [3][4][2] then head [2], [slot][lane]
+  const u32x4* hi;         // LDS (HL): hi parts, the same layout
   int lane;
 
   __device__ __forceinline__ v8 Al(int l, int b, int c) const {
@@ -126,19 +129,33 @@ struct NetRegsX3 {
   __device__ __forceinline__ v8 Ahl(int c) const {
     return __builtin_bit_cast(v8, lo[(24 + c) * 64 + lane]);
   }
+  __device__ __forceinline__ v8 Ahi(int l, int b, int c) const {
+    if constexpr (HL) return __builtin_bit_cast(v8, hi[((l * 4 + b) * 2 + c) * 64 + lane]);
+    else return A[l][b][c];
+  }
+  __device__ __forceinline__ v8 Ahh(int c) const {
+    if constexpr (HL) return __builtin_bit_cast(v8, hi[(24 + c) * 64 + lane]);
+    else return Ah[c];
+  }
 
   __device__ __forceinline__ void load(const u32x4* __restrict__ wp, int ln, f32x4* lds,
-                                       u32x4* lo_lds) {
+                                       u32x4* lo_lds, u32x4* hi_lds = nullptr) {
     lane = ln;
     int s = 0;
+    if constexpr (HL) {
+      for (int i = threadIdx.x; i < 26 * 64; i += blockDim.x) hi_lds[i] = wp[i];
+      hi = hi_lds;
+      s = 26;
+    } else {
 #pragma unroll
-    for (int l = 0; l < 3; ++l)
+      for (int l = 0; l < 3; ++l)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) A[l][b][c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
+          for (int c = 0; c < 2; ++c) A[l][b][c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
 #pragma unroll
-    for (int c = 0; c < 2; ++c) Ah[c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
+      for (int c = 0; c < 2; ++c) Ah[c] = __builtin_bit_cast(v8, wp[(s++) * 64 + lane]);
+    }
     const int s_bias = s;
     s += kBiasSlots;
     for (int i = threadIdx.x; i < 26 * 64; i += blockDim.x) lo_lds[i] = wp[s * 64 + i];
@@ -147,8 +164,8 @@ struct NetRegsX3 {
   }
 };
 
-template <int P, int ACT>
-__device__ __forceinline__ f32x4 chain_x3(const NetRegsX3<P>& R, const f32x4 z[4]) {
+template <int P, int ACT, bool HL>
+__device__ __forceinline__ f32x4 chain_x3(const NetRegsX3<P, HL>& R, const f32x4 z[4]) {
   BiasLds::pin();
   typedef typename Split16<P>::v8 v8;
   constexpr int B = Split16<P>::base;
@@ -163,22 +180,22 @@ __device__ __forceinline__ f32x4 chain_x3(const NetRegsX3<P>& R, const f32x4 z[4
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.Al(l, b, 1), h1, acc[b]);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.A[l][b][0], l0, acc[b]);
+    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.Ahi(l, b, 0), l0, acc[b]);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.A[l][b][1], l1, acc[b]);
+    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.Ahi(l, b, 1), l1, acc[b]);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.A[l][b][0], h0, acc[b]);
+    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.Ahi(l, b, 0), h0, acc[b]);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.A[l][b][1], h1, acc[b]);
+    for (int b = 0; b < 4; ++b) acc[b] = H16<B>::mfma(R.Ahi(l, b, 1), h1, acc[b]);
     split8<P, ACT>(acc[0], acc[1], h0, l0);
     split8<P, ACT>(acc[2], acc[3], h1, l1);
   }
   f32x4 y = H16<B>::mfma(R.Ahl(0), h0, R.C.head(R.lane));
   y = H16<B>::mfma(R.Ahl(1), h1, y);
-  y = H16<B>::mfma(R.Ah[0], l0, y);
-  y = H16<B>::mfma(R.Ah[1], l1, y);
-  y = H16<B>::mfma(R.Ah[0], h0, y);
-  return H16<B>::mfma(R.Ah[1], h1, y);
+  y = H16<B>::mfma(R.Ahh(0), l0, y);
+  y = H16<B>::mfma(R.Ahh(1), l1, y);
+  y = H16<B>::mfma(R.Ahh(0), h0, y);
+  return H16<B>::mfma(R.Ahh(1), h1, y);
 }
 
 // Two independent 16-path groups (a, b) through the same chain, written so
@@ -187,8 +204,8 @@ __device__ __forceinline__ f32x4 chain_x3(const NetRegsX3<P>& R, const f32x4 z[4
 // in flight issues its own independent VALU work, so one group's bias, ReLU
 // and split run while the other group's products are computed.  Every value
 // is the one the single-group chain computes.
-template <int P, int ACT>
-__device__ __forceinline__ void chain_x3_pair(const NetRegsX3<P>& R, const f32x4 za[4],
+template <int P, int ACT, bool HL>
+__device__ __forceinline__ void chain_x3_pair(const NetRegsX3<P, HL>& R, const f32x4 za[4],
                                               const f32x4 zb[4], f32x4& ya, f32x4& yb) {
   BiasLds::pin();
   typedef typename Split16<P>::v8 v8;
@@ -207,16 +224,16 @@ __device__ __forceinline__ void chain_x3_pair(const NetRegsX3<P>& R, const f32x4
       const v8 wl0 = R.Al(l, b, 0), wl1 = R.Al(l, b, 1);
       aa[b] = H16<B>::mfma(wl0, ha0, c);
       aa[b] = H16<B>::mfma(wl1, ha1, aa[b]);
-      aa[b] = H16<B>::mfma(R.A[l][b][0], la0, aa[b]);
-      aa[b] = H16<B>::mfma(R.A[l][b][1], la1, aa[b]);
-      aa[b] = H16<B>::mfma(R.A[l][b][0], ha0, aa[b]);
-      aa[b] = H16<B>::mfma(R.A[l][b][1], ha1, aa[b]);
+      aa[b] = H16<B>::mfma(R.Ahi(l, b, 0), la0, aa[b]);
+      aa[b] = H16<B>::mfma(R.Ahi(l, b, 1), la1, aa[b]);
+      aa[b] = H16<B>::mfma(R.Ahi(l, b, 0), ha0, aa[b]);
+      aa[b] = H16<B>::mfma(R.Ahi(l, b, 1), ha1, aa[b]);
       ab[b] = H16<B>::mfma(wl0, hb0, c);
       ab[b] = H16<B>::mfma(wl1, hb1, ab[b]);
-      ab[b] = H16<B>::mfma(R.A[l][b][0], lb0, ab[b]);
-      ab[b] = H16<B>::mfma(R.A[l][b][1], lb1, ab[b]);
-      ab[b] = H16<B>::mfma(R.A[l][b][0], hb0, ab[b]);
-      ab[b] = H16<B>::mfma(R.A[l][b][1], hb1, ab[b]);
+      ab[b] = H16<B>::mfma(R.Ahi(l, b, 0), lb0, ab[b]);
+      ab[b] = H16<B>::mfma(R.Ahi(l, b, 1), lb1, ab[b]);
+      ab[b] = H16<B>::mfma(R.Ahi(l, b, 0), hb0, ab[b]);
+      ab[b] = H16<B>::mfma(R.Ahi(l, b, 1), hb1, ab[b]);
     }
     split8<P, ACT>(aa[0], aa[1], ha0, la0);
     split8<P, ACT>(aa[2], aa[3], ha1, la1);
@@ -227,16 +244,16 @@ __device__ __forceinline__ void chain_x3_pair(const NetRegsX3<P>& R, const f32x4
   const v8 wl0 = R.Ahl(0), wl1 = R.Ahl(1);
   ya = H16<B>::mfma(wl0, ha0, c);
   ya = H16<B>::mfma(wl1, ha1, ya);
-  ya = H16<B>::mfma(R.Ah[0], la0, ya);
-  ya = H16<B>::mfma(R.Ah[1], la1, ya);
-  ya = H16<B>::mfma(R.Ah[0], ha0, ya);
-  ya = H16<B>::mfma(R.Ah[1], ha1, ya);
+  ya = H16<B>::mfma(R.Ahh(0), la0, ya);
+  ya = H16<B>::mfma(R.Ahh(1), la1, ya);
+  ya = H16<B>::mfma(R.Ahh(0), ha0, ya);
+  ya = H16<B>::mfma(R.Ahh(1), ha1, ya);
   yb = H16<B>::mfma(wl0, hb0, c);
   yb = H16<B>::mfma(wl1, hb1, yb);
-  yb = H16<B>::mfma(R.Ah[0], lb0, yb);
-  yb = H16<B>::mfma(R.Ah[1], lb1, yb);
-  yb = H16<B>::mfma(R.Ah[0], hb0, yb);
-  yb = H16<B>::mfma(R.Ah[1], hb1, yb);
+  yb = H16<B>::mfma(R.Ahh(0), lb0, yb);
+  yb = H16<B>::mfma(R.Ahh(1), lb1, yb);
+  yb = H16<B>::mfma(R.Ahh(0), hb0, yb);
+  yb = H16<B>::mfma(R.Ahh(1), hb1, yb);
 }
 
 template <int P, int ACT>
@@ -503,10 +520,12 @@ struct NetF {
   __device__ __forceinline__ void eval_pair(float, float, const f32x4*, f32x4&, f32x4&) const {}
 };
 
-template <int P, int ACT>
+template <int P, int ACT, bool HL = false>
 struct NetX3 {
-  NetRegsX3<P> R;
-  __device__ __forceinline__ f32x4 eval_z0(const f32x4 z[4]) const { return chain_x3<P, ACT>(R, z); }
+  NetRegsX3<P, HL> R;
+  __device__ __forceinline__ f32x4 eval_z0(const f32x4 z[4]) const {
+    return chain_x3<P, ACT, HL>(R, z);
+  }
   static constexpr bool kPair = true;
   __device__ __forceinline__ void eval_pair(float Ya, float Yb, const f32x4* c0, f32x4& ya,
                                             f32x4& yb) const {
@@ -521,7 +540,7 @@ struct NetX3 {
         zb[b][r] = fmaf(Yb, w[r], c[r]);
       }
     }
-    chain_x3_pair<P, ACT>(R, za, zb, ya, yb);
+    chain_x3_pair<P, ACT, HL>(R, za, zb, ya, yb);
   }
 };
 
@@ -568,6 +587,20 @@ __global__ __launch_bounds__(256) void k_sim_mfma_x3(SimArgs a) {
   sim_persistent(a, net, c0_lds);
 }
 
+// The same with every weight in LDS, for 12-wave workgroups (three waves per
+// SIMD): each product then waits on an LDS read, which pays where the chip
+// is full and costs where a few blocks run alone.
+template <int P, int ACT>
+__global__ __launch_bounds__(64 * kWavesX3L) void k_sim_mfma_x3l(SimArgs a) {
+  __shared__ f32x4 bias_lds[kBiasSlots * 64];
+  __shared__ u32x4 lo_lds[26 * 64];
+  __shared__ u32x4 hi_lds[26 * 64];
+  __shared__ f32x4 c0_lds[kWavesX3L * 256];
+  NetX3<P, ACT, true> net;
+  net.R.load((const u32x4*)a.wpack, threadIdx.x & 63, bias_lds, lo_lds, hi_lds);
+  sim_persistent(a, net, c0_lds);
+}
+
 template <int ACT>
 __global__ __launch_bounds__(256) void k_sim_mfma_f(SimArgs a) {
   __shared__ f32x4 bias_lds[kBiasSlots * 64];
@@ -580,6 +613,10 @@ template <int ACT>
 static void launch_sim_mfma_act(int prec, const SimArgs& a, dim3 g, dim3 b, hipStream_t s) {
   if (prec == SL7_BF16) hipLaunchKernelGGL((k_sim_mfma_h<SL7_BF16, ACT>), g, b, 0, s, a);
   else if (prec == SL7_F16) hipLaunchKernelGGL((k_sim_mfma_h<SL7_F16, ACT>), g, b, 0, s, a);
+  else if (prec == SL7_BF16X3 && b.x == 64 * kWavesX3L)
+    hipLaunchKernelGGL((k_sim_mfma_x3l<SL7_BF16X3, ACT>), g, b, 0, s, a);
+  else if (prec == SL7_F16X3 && b.x == 64 * kWavesX3L)
+    hipLaunchKernelGGL((k_sim_mfma_x3l<SL7_F16X3, ACT>), g, b, 0, s, a);
   else if (prec == SL7_BF16X3) hipLaunchKernelGGL((k_sim_mfma_x3<SL7_BF16X3, ACT>), g, b, 0, s, a);
   else if (prec == SL7_F16X3) hipLaunchKernelGGL((k_sim_mfma_x3<SL7_F16X3, ACT>), g, b, 0, s, a);
   else hipLaunchKernelGGL((k_sim_mfma_f<ACT>), g, b, 0, s, a);

@@ -95,12 +95,16 @@ extern "C" int sl7_simulate_noalloc(const sl7_problem* pr, const sl7_mlp* Hc, in
     return fail(SL7_EINVAL, "sl7_simulate_noalloc: pr.N=%lld exceeds the fixed scratch "
                             "(at most %lld paths)", (long long)pr->N,
                 (long long)(kStMaxBlocks * 64));
-  sl7_plan plan;
-  if (plan_in) plan = *plan_in; else default_plan(prec, &plan);
-  rc = check_plan(&plan);
-  if (rc) return rc;
   int dev;
   rc = current_device(&dev);
+  if (rc) return rc;
+  unsigned char* base;
+  int n_cu;
+  rc = static_scratch(dev, &base, &n_cu);
+  if (rc) return rc;
+  sl7_plan plan;
+  if (plan_in) plan = *plan_in; else default_plan(prec, blocks, n_cu, &plan);
+  rc = check_plan(&plan, prec);
   if (rc) return rc;
   if (H) {
     // the network's device copy must exist already: creating it allocates
@@ -111,10 +115,6 @@ extern "C" int sl7_simulate_noalloc(const sl7_problem* pr, const sl7_mlp* Hc, in
                               "%d (one sl7_simulate or sl7_eval_H call with it makes one)",
                   prec, dev);
   }
-  unsigned char* base;
-  int n_cu;
-  rc = static_scratch(dev, &base, &n_cu);
-  if (rc) return rc;
   SimArgs a;
   std::memset(&a, 0, sizeof(a));
   double x[SL7_MAX_M];

@@ -136,8 +136,11 @@ int64_t n_params_of(const sl7_mlp_desc& d);
 int upload_lane_layout(const Mlp& H, std::unique_ptr<DevBuf>& net, std::unique_ptr<DevBuf>& wth);
 int check_desc(const sl7_mlp_desc* d);
 int check_problem(const sl7_problem* pr, const Mlp* H, int prec, const char* name);
-int check_plan(const sl7_plan* p);
-int default_plan(int prec, sl7_plan* p);
+int check_plan(const sl7_plan* p, int prec);
+// The default launch plan for a launch of n_blocks 64-path blocks on n_cu
+// compute units (n_blocks < 0: size not known).
+int default_plan(int prec, int64_t n_blocks, int n_cu, sl7_plan* p);
+int64_t total_blocks(const sl7_problem* prs, int n);
 // pwl_theta: in the PWL modes, build the adjoint's records (with theta
 // derivatives) instead of the simulation's.
 int prepare_instances(const sl7_problem* prs, int n, const Mlp* H, int prec, uint64_t seed,

@@ -80,6 +80,11 @@ constexpr int kSlotsF = 48 + 4 + 12 + 1 + 4;  // 69
 constexpr int kSlotsX3 = kSlotsH + 24 + 2;    // 69
 
 inline bool is_x3(int prec) { return prec == SL7_BF16X3 || prec == SL7_F16X3; }
+// Waves per workgroup of the split modes' all-LDS simulation kernel (the
+// other fused kernels take 1, 2 or 4).
+constexpr int kWavesX3L = 12;
+// 64-path blocks per compute unit from which the default plan takes it.
+constexpr int kX3LBlocksPerCu = 64;
 inline bool is_pwl(int prec) { return prec == SL7_PWL32 || prec == SL7_PWL64; }
 
 // Piece record of the piecewise-linear form, in the lane arithmetic's type:

@@ -146,8 +146,10 @@ def test_plans_beyond_the_kernels_launch_bounds_are_rejected(L):
     import paper_2302_05170_amd as S
     H = S.Mlp.load(WEIGHTS)
     pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 4, 5, 100).c()
-    for bad in (dict(waves_per_block=8), dict(waves_per_block=3), dict(blocks_per_cu=0),
-                dict(grab=0)):
+    # L.BF16 (one pass) takes at most four waves per workgroup; 12 is for
+    # the split modes only
+    for bad in (dict(waves_per_block=8), dict(waves_per_block=3), dict(waves_per_block=12),
+                dict(blocks_per_cu=0), dict(grab=0)):
         plan = L.Plan()
         plan.waves_per_block, plan.blocks_per_cu, plan.grab = 4, 1, 1
         for k, v in bad.items():

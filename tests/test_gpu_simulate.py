@@ -206,11 +206,15 @@ def test_gbm_2p24x32_bf16x3_equal_weak_error_to_f32(S, H):
 def test_results_independent_of_launch_plan(S, H):
     c = W.CONFIGS["gbm_mlp_2p22x16"]
     pr = S.Problem(c["model"], c["theta"], c["Y0"], c["T"], 9, c["m"], 50_001, K=c["K"])
-    for prec in ("bf16", "f32", "bf16x3"):
+    for prec in ("bf16", "f32", "bf16x3", "f16x3"):
         outs = []
-        for plan in (None, dict(waves_per_block=1, blocks_per_cu=1, grab=1),
-                     dict(waves_per_block=4, blocks_per_cu=1, grab=7),
-                     dict(waves_per_block=2, blocks_per_cu=3, grab=2)):
+        plans = [None, dict(waves_per_block=1, blocks_per_cu=1, grab=1),
+                 dict(waves_per_block=4, blocks_per_cu=1, grab=7),
+                 dict(waves_per_block=2, blocks_per_cu=3, grab=2)]
+        if prec.endswith("x3"):  # the split modes' all-LDS kernel: 12-wave workgroups
+            plans += [dict(waves_per_block=12, blocks_per_cu=1, grab=1),
+                      dict(waves_per_block=12, blocks_per_cu=2, grab=3)]
+        for plan in plans:
             st, y = gpu_yt(S, pr, H, prec, 77, plan=plan)
             outs.append((st, y))
         for st, y in outs[1:]:
