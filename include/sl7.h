@@ -357,6 +357,15 @@ int sl7_train(sl7_mlp* H, const sl7_train_spec* spec, const float* X_dev,
 int sl7_train_grad(const sl7_mlp* H, const float* X_dev, const float* Y_dev, int64_t B,
                    float* grad_dev, double* loss_host, void* stream);
 
+/* --- launch plans ------------------------------------------------------ */
+/* The plan a call uses when it is given none, for a launch of n_blocks
+ * 64-path blocks (the sum of ceil(N / 64) over its instances) on a device
+ * with n_cu compute units.  Host only, no device needed.  The split modes
+ * take 12-wave workgroups (all weights in LDS) from 64 blocks per compute
+ * unit, 4-wave ones below.  SL7_EINVAL for an unknown precision, n_cu < 1
+ * or out == NULL. */
+int sl7_default_plan(int prec, int64_t n_blocks, int n_cu, sl7_plan* out);
+
 /* --- launch-plan autotuner -------------------------------------------- */
 /* Times candidate plans on `shape` (a problem, N may be reduced) and
  * returns the fastest in *out; when cache_path is not NULL the result is

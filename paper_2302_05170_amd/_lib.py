@@ -60,6 +60,7 @@ SIGNATURES = {
     "sl7_pwl_compile": (ctypes.c_int, [c_p, c_p, ctypes.c_int, c_p, c_p, c_p, c_p, c_p]),
     "sl7_simulate_batched": (ctypes.c_int, [c_p, ctypes.c_int, c_p, ctypes.c_int, c_u64, c_p, c_p,
                                             ctypes.c_int, c_p]),
+    "sl7_default_plan": (ctypes.c_int, [ctypes.c_int, c_i64, ctypes.c_int, c_p]),
     "sl7_autotune": (ctypes.c_int, [c_p, c_p, ctypes.c_int, ctypes.c_char_p, c_p, c_p]),
     "sl7_autotune_batched": (ctypes.c_int, [c_p, ctypes.c_int, c_p, ctypes.c_int, ctypes.c_char_p,
                                             c_p, c_p]),

@@ -638,6 +638,18 @@ int default_plan(int prec, int64_t n_blocks, int n_cu, sl7_plan* p) {
   return SL7_OK;
 }
 
+}  // namespace sl7
+
+extern "C" int sl7_default_plan(int prec, int64_t n_blocks, int n_cu, sl7_plan* out) {
+  using namespace sl7;
+  if (!out) return fail(SL7_EINVAL, "out is NULL");
+  if (n_cu < 1) return fail(SL7_EINVAL, "n_cu=%d", n_cu);
+  if (prec < SL7_F64 || prec > SL7_PWL64) return fail(SL7_EINVAL, "prec=%d unknown", prec);
+  return default_plan(prec, n_blocks, n_cu, out);
+}
+
+namespace sl7 {
+
 int check_plan(const sl7_plan* p, int prec) {
   // the fused kernels are compiled for at most 256 threads per workgroup,
   // the split modes' all-LDS kernel for 768

@@ -241,3 +241,25 @@ def test_binding_refuses_tensors_it_cannot_size(L):
     pr = S.Problem(W.GBM, (0.3, 0.1), 1.0, 1.0, 4, 5, 100)
     with pytest.raises(ValueError, match="yt must be"):
         S.simulate(pr, None, prec="f32", yt=torch.empty(100))
+
+
+def test_default_plan_takes_the_all_lds_split_kernel_for_large_launches(L):
+    """sl7_default_plan (host only): the split modes run 12-wave workgroups
+    from 64 blocks of 64 paths per compute unit and 4-wave ones below; no
+    other mode takes 12 waves; every default passes the calls' own checks."""
+    def plan(prec, blocks, n_cu=256):
+        p = L.Plan()
+        L.check(L.lib().sl7_default_plan(prec, blocks, n_cu, ctypes.byref(p)))
+        return (p.waves_per_block, p.blocks_per_cu, p.grab)
+    for prec in (L.BF16X3, L.F16X3):
+        assert plan(prec, 64 * 256) == (12, 1, 1)
+        assert plan(prec, 2 ** 18) == (12, 1, 1)
+        assert plan(prec, 64 * 256 - 1)[0] == 4
+        assert plan(prec, 3125)[0] == 4  # the paper's OU shape, 2e5 paths
+        assert plan(prec, 64 * 80, n_cu=80) == (12, 1, 1)
+    for prec in (L.F32, L.BF16, L.F16, L.PWL32, L.PWL64, L.F64):
+        assert plan(prec, 2 ** 20)[0] in (1, 2, 4)
+    p = L.Plan()
+    assert L.lib().sl7_default_plan(L.BF16X3, 100, 0, ctypes.byref(p)) == L.SL7_EINVAL
+    assert L.lib().sl7_default_plan(99, 100, 256, ctypes.byref(p)) == L.SL7_EINVAL
+    assert L.lib().sl7_default_plan(L.BF16X3, 100, 256, None) == L.SL7_EINVAL
