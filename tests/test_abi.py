@@ -4,6 +4,7 @@ header states.  No GPU work is launched here."""
 import ctypes
 import os
 import re
+import subprocess
 import tempfile
 
 import numpy as np
@@ -263,3 +264,38 @@ def test_default_plan_takes_the_all_lds_split_kernel_for_large_launches(L):
     assert L.lib().sl7_default_plan(L.BF16X3, 100, 0, ctypes.byref(p)) == L.SL7_EINVAL
     assert L.lib().sl7_default_plan(99, 100, 256, ctypes.byref(p)) == L.SL7_EINVAL
     assert L.lib().sl7_default_plan(L.BF16X3, 100, 256, None) == L.SL7_EINVAL
+
+
+def test_c_program_links_and_calls_host_entry_points(L, tmp_path):
+    """The boundary is plain C: a C99 program includes sl7.h, links
+    libsl7.so and calls two host-only entry points (no device needed): the
+    Gauss-Hermite nodes for m = 3 (0, +-sqrt(3)) and the default plan."""
+    import shutil
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "abi_check.c"
+    src.write_text(r'''
+#include <math.h>
+#include <stdio.h>
+#include "sl7.h"
+int main(void) {
+  double x[3], w[3];
+  if (sl7_gh_nodes(3, x, w) != SL7_OK) return 1;
+  if (fabs(x[0] + sqrt(3.0)) > 1e-14 || fabs(x[1]) > 1e-15 || fabs(x[2] - sqrt(3.0)) > 1e-14)
+    return 2;
+  sl7_plan p;
+  if (sl7_default_plan(SL7_BF16X3, 1 << 20, 256, &p) != SL7_OK || p.waves_per_block != 12) return 3;
+  if (sl7_default_plan(SL7_F32, 1 << 20, 256, &p) != SL7_OK || p.waves_per_block != 4) return 4;
+  if (sl7_default_plan(SL7_F32, 1, 0, &p) != SL7_EINVAL) return 5;
+  printf("ok %s\n", sl7_version());
+  return 0;
+}
+''')
+    exe = tmp_path / "abi_check"
+    libdir = os.path.dirname(L.LIB_PATH)
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                        str(src), "-o", str(exe), "-L", libdir, "-lsl7", "-lm",
+                        f"-Wl,-rpath,{libdir}"], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.startswith("ok"), (r.returncode, r.stdout, r.stderr)
